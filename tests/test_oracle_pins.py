@@ -1,0 +1,366 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Every check here is fixed by the paper or by mathematics: hand-derived closed
+forms of the first shells, the exact-distance sandwich for constant speed,
+local causality and the residual of the upwind scheme Eq. (2)-(3), the fixed
+point of the same scheme found without heap, tags or the closed-form root
+(Gauss-Seidel and Jacobi with a bisection root), symmetry, exact scaling by
+powers of two, monotone acceptance (Sec. 2.1), the comparison principle, and
+the paper's own statements about the block method (Sec. 2.4, 2.5, 3.2, 3.4).
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import oracle
+from paper_1811_00009_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EPS64 = np.finfo(np.float64).eps
+
+
+def _first_shells():
+    rows, env = [], {"sqrt": math.sqrt}
+    with open(os.path.join(GOLDEN, "first_shells.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            di, dj, dk, name, expr = line.split(maxsplit=4)
+            env[name] = eval(expr, {"__builtins__": {}}, env)
+            rows.append(((int(di), int(dj), int(dk)), name, env[name]))
+    return rows
+
+
+def _signed_perms(o):
+    out = set()
+    for perm in itertools.permutations(o):
+        for signs in itertools.product((1, -1), repeat=3):
+            out.add(tuple(s * v for s, v in zip(signs, perm)))
+    return sorted(out)
+
+
+# ----------------------------------------------------------------------- P1, P7
+@pytest.mark.parametrize("F0,h", [(1.0, 1.0), (2.0, 0.125), (0.5, 1.0 / 63)])
+def test_first_shells_closed_form(F0, h):
+    n, c = 11, 5
+    F = np.full((n, n, n), F0)
+    psi = oracle.fmm(F, h, [(c, c, c)])
+    unit = h / F0
+    for off, name, val in _first_shells():
+        for o in _signed_perms(off):
+            got = psi[c + o[2], c + o[1], c + o[0]]
+            assert abs(got - val * unit) <= 4 * EPS64 * val * unit, (name, o, got, val * unit)
+
+
+def test_symmetry_bitwise():
+    """Constant speed, centred source: psi depends only on the sorted |offset|."""
+    n, c = 13, 6
+    psi = oracle.fmm(np.full((n, n, n), 1.3), 0.1, [(c, c, c)])
+    for k in range(n):
+        for j in range(n):
+            for i in range(n):
+                key = tuple(sorted((abs(i - c), abs(j - c), abs(k - c))))
+                ref = psi[c + key[2], c + key[1], c + key[0]]
+                assert psi[k, j, i] == ref
+
+
+# ----------------------------------------------------------------------- P8
+def test_power_of_two_scaling_bitwise():
+    p = inputs.random_problem(3, shape=(12, 10, 9), nsrc=2)
+    a = oracle.fmm(p.F, p.h, p.sources)
+    b = oracle.fmm(2.0 * p.F, p.h, p.sources)
+    c = oracle.fmm(p.F, 2.0 * p.h, p.sources)
+    assert np.array_equal(b, a / 2)
+    assert np.array_equal(c, a * 2)
+
+
+# ----------------------------------------------------------------------- P2
+@pytest.mark.parametrize("shape,src", [((20, 17, 23), (3, 11, 14)), ((9, 30, 12), (11, 2, 5))])
+def test_exact_distance_sandwich(shape, src):
+    """Constant F: |x-x0|_2 / F <= psi <= |x-x0|_1 / F (first-order upwind bounds)."""
+    nz, ny, nx = shape
+    h, F0 = 0.05, 1.7
+    psi = oracle.fmm(np.full(shape, F0), h, [src])
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    dx, dy, dz = (i - src[0]) * h, (j - src[1]) * h, (k - src[2]) * h
+    l2 = np.sqrt(dx * dx + dy * dy + dz * dz) / F0
+    l1 = (np.abs(dx) + np.abs(dy) + np.abs(dz)) / F0
+    slack = 8 * EPS64 * np.maximum(l1, 1e-300)
+    assert np.all(psi >= l2 - slack)
+    assert np.all(psi <= l1 + slack)
+    # axis points are exact sums of h/F
+    di = 3 if src[0] + 3 < nx else -3
+    assert psi[src[2], src[1], src[0] + di] == pytest.approx(3 * h / F0, rel=4 * EPS64)
+
+
+def test_first_order_error_decreases_with_refinement():
+    """max(psi - d) at the common physical points shrinks as h -> 0 (first-order scheme)."""
+    errs = []
+    for n in (17, 33, 65):
+        h = 1.0 / (n - 1)
+        c = (n - 1) // 4
+        psi = oracle.fmm(np.ones((n, n, n)), h, [(c, c, c)])
+        x = np.arange(n) * h
+        d = np.sqrt((x[None, None, :] - c * h) ** 2 + (x[None, :, None] - c * h) ** 2
+                    + (x[:, None, None] - c * h) ** 2)
+        s = (n - 1) // 16  # the 17^3 physical points
+        errs.append(float(np.max((psi - d)[::s, ::s, ::s])))
+    assert errs[0] > errs[1] > errs[2] > 0
+    # first order with the point-source log factor: error / (h log(1/h)) stays bounded
+    for e, n in zip(errs, (17, 33, 65)):
+        h = 1.0 / (n - 1)
+        assert e <= 2.0 * h * math.log(1 / h)
+
+
+# ----------------------------------------------------------------------- P3, P4
+def _neighbour_minima(psi):
+    big = np.full_like(psi, np.inf)
+    a = []
+    for axis in (2, 1, 0):
+        lo, hi = big.copy(), big.copy()
+        sl_lo = [slice(None)] * 3
+        sl_src = [slice(None)] * 3
+        sl_lo[axis], sl_src[axis] = slice(1, None), slice(None, -1)
+        lo[tuple(sl_lo)] = psi[tuple(sl_src)]
+        sl_hi = [slice(None)] * 3
+        sl_src2 = [slice(None)] * 3
+        sl_hi[axis], sl_src2[axis] = slice(None, -1), slice(1, None)
+        hi[tuple(sl_hi)] = psi[tuple(sl_src2)]
+        a.append(np.minimum(lo, hi))
+    return a
+
+
+def _source_mask(shape, sources):
+    m = np.zeros(shape, dtype=bool)
+    for s in sources:
+        m[s[2], s[1], s[0]] = True
+    return m
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_local_causality_and_residual(seed):
+    p = inputs.random_problem(seed, shape=(18, 21, 16), nsrc=3, flo=0.3, fhi=2.5)
+    psi = oracle.fmm(p.F, p.h, p.sources)
+    a = _neighbour_minima(psi)
+    amin = np.minimum(np.minimum(a[0], a[1]), a[2])
+    mask = ~_source_mask(p.shape, p.sources) & np.isfinite(psi)
+    inc = (psi - amin)[mask]
+    hf = (p.h / p.F)[mask]
+    tol = 64 * EPS64 * psi[mask]
+    # P3: h/(F sqrt 3) <= psi_p - min_nb psi <= h/F
+    assert np.all(inc >= hf / math.sqrt(3) - tol)
+    assert np.all(inc <= hf + tol)
+    # P4: residual of Eq. (2) with Eq. (3) at every reached non-source point
+    s = np.zeros_like(psi)
+    for ad in a:
+        u = np.where(psi > ad, (psi - ad) / p.h, 0.0)
+        s += u * u
+    res = (s - 1.0 / p.F ** 2)[mask] * (p.h / (1 / p.F[mask])) ** 2
+    assert np.max(np.abs(res)) <= 1e-12
+
+
+# ----------------------------------------------------------------------- P5, P6
+@pytest.mark.parametrize("seed", range(6))
+def test_gauss_seidel_fixed_point(seed):
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(v) for v in rng.integers(3, 9, size=3))
+    p = inputs.random_problem(seed, shape=shape, nsrc=int(rng.integers(1, 4)), flo=0.25, fhi=2.0)
+    psi = oracle.fmm(p.F, p.h, p.sources)
+    gs = oracle.gauss_seidel(p.F, p.h, p.sources)
+    assert np.array_equal(np.isinf(psi), np.isinf(gs))
+    fin = np.isfinite(psi)
+    assert np.max(np.abs(psi[fin] - gs[fin])) <= 64 * EPS64 * np.max(psi[fin])
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_jacobi_fixed_point(seed):
+    rng = np.random.default_rng(100 + seed)
+    shape = tuple(int(v) for v in rng.integers(2, 7, size=3))
+    p = inputs.random_problem(100 + seed, shape=shape, nsrc=int(rng.integers(1, 3)))
+    psi = oracle.fmm(p.F, p.h, p.sources)
+    jb = oracle.jacobi(p.F, p.h, p.sources)
+    fin = np.isfinite(psi)
+    assert np.max(np.abs(psi[fin] - jb[fin])) <= 64 * EPS64 * np.max(psi[fin])
+
+
+def test_bisection_root_matches_library_root():
+    """The fixed-point checks' local root agrees with scipy's brentq on Eq. (2)."""
+    p = inputs.random_problem(7, shape=(5, 5, 5), nsrc=1)
+    gs = oracle.gauss_seidel(p.F, p.h, p.sources)
+    a = _neighbour_minima(gs)
+    src = _source_mask(p.shape, p.sources)
+    for (k, j, i) in [(1, 2, 3), (4, 4, 0), (2, 0, 1)]:
+        if src[k, j, i]:
+            continue
+        ad = [a[d][k, j, i] for d in range(3)]
+        lo = min(ad)
+
+        def g(t):
+            return sum(max(t - x, 0.0) ** 2 for x in ad) - (p.h / p.F[k, j, i]) ** 2
+        root = brentq(g, lo, lo + p.h / p.F[k, j, i] * (1 + 1e-9), xtol=1e-300, rtol=4 * EPS64)
+        assert gs[k, j, i] == pytest.approx(root, rel=1e-14)
+
+
+# ----------------------------------------------------------------------- P9, P10
+def test_monotone_pops_and_count():
+    p = inputs.random_problem(11, shape=(14, 9, 12), nsrc=2)
+    psi, st = oracle.fmm(p.F, p.h, p.sources, stats=True)
+    assert st["nonmonotone_pops"] == 0
+    assert st["pops"] == int(np.isfinite(psi).sum())  # every reached point accepted once
+
+
+def test_comparison_principle():
+    p = inputs.random_problem(12, shape=(12, 12, 12), nsrc=2)
+    rng = np.random.default_rng(5)
+    F2 = p.F * (1.0 + rng.uniform(0.0, 0.5, size=p.F.shape))
+    a = oracle.fmm(p.F, p.h, p.sources)
+    b = oracle.fmm(F2, p.h, p.sources)
+    assert np.all(a >= b - 1e-14)
+
+
+# ----------------------------------------------------------------------- obstacles, width, psi0
+def test_obstacles_are_never_solved():
+    n = 12
+    F = np.ones((n, n, n))
+    F[:, :, 6] = 0.0  # a wall at i = 6 separates the grid in two halves
+    psi = oracle.fmm(F, 0.1, [(2, 5, 5)])
+    assert np.all(np.isinf(psi[:, :, 6:]))
+    assert np.all(np.isfinite(psi[:, :, :6]))
+
+
+def test_narrow_band_width_is_exact_below_width():
+    p = inputs.random_problem(21, shape=(16, 16, 16), nsrc=2)
+    full = oracle.fmm(p.F, p.h, p.sources)
+    W = float(np.quantile(full[np.isfinite(full)], 0.3))
+    part = oracle.fmm(p.F, p.h, p.sources, width=W)
+    inside = full <= W
+    assert np.array_equal(part[inside], full[inside])
+    assert np.all(part[~inside] > W)
+
+
+def test_source_values_and_duplicates():
+    F = np.ones((7, 7, 7))
+    psi = oracle.fmm(F, 1.0, [(1, 1, 1, 0.5), (1, 1, 1, 0.25), (5, 5, 5, 2.0)])
+    assert psi[1, 1, 1] == 0.25
+    assert psi[5, 5, 5] == 2.0
+    assert psi[1, 1, 2] == 1.25
+
+
+# ----------------------------------------------------------------------- formula reading
+def test_shifted_root_matches_literal_coefficients():
+    """Alg. 3's literal coefficients and the shifted form give the same field in FP64."""
+    p = inputs.random_problem(31, shape=(20, 20, 20), nsrc=2)
+    a = oracle.fmm(p.F, p.h, p.sources)
+    b = oracle.fmm(p.F, p.h, p.sources, literal=True)
+    assert np.max(np.abs(a - b)) <= 1e-12
+    # and in FP32 the literal coefficients lose accuracy the shifted form keeps
+    a32 = oracle.fmm(p.F, p.h, p.sources, dtype=np.float32)
+    assert np.max(np.abs(a32 - a)) <= 1e-5 * np.max(a)
+
+
+# ----------------------------------------------------------------------- block method (Alg. 6)
+def test_single_block_equals_baseline_bitwise():
+    """Sec. 3.2: single-block solutions of the block solver and the baseline are identical."""
+    for dtype in (np.float64, np.float32):
+        p = inputs.random_problem(41, shape=(16, 16, 16), nsrc=2, dtype=dtype)
+        a = oracle.fmm(p.F, p.h, p.sources, dtype=dtype)
+        for stride in (0.5 * p.h, 2 * p.h, math.inf):
+            b = oracle.block_fmm(p.F, p.h, p.sources, block=16, stride=stride, dtype=dtype)
+            assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed,block,stride_h", [(50, 4, 2.0), (51, 8, 0.5), (52, 8, 3.5),
+                                                 (53, 4, math.inf), (54, 8, 1.5)])
+def test_block_method_matches_baseline(seed, block, stride_h):
+    """Sec. 3.2: multi-block results agree with the baseline to rounding level."""
+    p = inputs.random_problem(seed, shape=(16, 24, 16), nsrc=3, obstacles=0.05)
+    a = oracle.fmm(p.F, p.h, p.sources)
+    b = oracle.block_fmm(p.F, p.h, p.sources, block=block, stride=stride_h * p.h)
+    assert np.array_equal(np.isinf(a), np.isinf(b))
+    fin = np.isfinite(a)
+    assert np.max(np.abs(a[fin] - b[fin])) <= 1e-12
+
+
+def test_restart_counts_follow_paper():
+    """Sec. 3.4: for a preset stride the restart count does not depend on the block size,
+    and it is about psi_max / stride (restarts scale like grid size / stride).  This holds
+    in the paper's regime, strides of a few h and blocks of 8 or more points; a stride that
+    outruns a block needs one restart per block crossed (recorded below, not gated)."""
+    n = 64
+    F = np.ones((n, n, n))
+    h = 1.0 / (n - 1)
+    src = [(32, 32, 32)]
+    psi = oracle.fmm(F, h, src)
+    for sh in (0.5, 1.0, 2.0):
+        vals = [oracle.block_fmm(F, h, src, block=b, stride=sh * h, stats=True)[1]["restarts"]
+                for b in (8, 16, 32)]
+        assert max(vals) - min(vals) <= 1, (sh, vals)
+        expect = np.max(psi) / (sh * h)
+        assert all(expect <= v <= expect + 3 for v in vals), (sh, vals, expect)
+    # stride = inf: restarts grow with the number of blocks per axis (Sec. 3.4)
+    inf_counts = [oracle.block_fmm(F, h, src, block=b, stride=math.inf, stats=True)[1]["restarts"]
+                  for b in (32, 16, 8)]
+    assert inf_counts[0] < inf_counts[1] < inf_counts[2]
+
+
+def test_stride_infinite_is_plain_block_method():
+    """Sec. 2.4: stride = width restores the non-restarted block method; same psi."""
+    p = inputs.random_problem(60, shape=(16, 16, 16), nsrc=2)
+    a = oracle.block_fmm(p.F, p.h, p.sources, block=8, stride=2 * p.h)
+    b, st = oracle.block_fmm(p.F, p.h, p.sources, block=8, stride=math.inf, stats=True)
+    assert np.max(np.abs(a - b)) <= 1e-12
+    assert st["restarts"] >= 2
+
+
+def test_given_bound_sequence_same_psi():
+    """Any increasing bound sequence gives the same solution (the stride only schedules)."""
+    p = inputs.random_problem(61, shape=(16, 16, 16), nsrc=1)
+    a = oracle.block_fmm(p.F, p.h, p.sources, block=8, stride=2 * p.h)
+    rng = np.random.default_rng(0)
+    bounds = np.cumsum(rng.uniform(0.25, 8.0, size=40) * 2 * p.h)
+    b = oracle.block_fmm(p.F, p.h, p.sources, block=8, stride=2 * p.h, bounds=bounds)
+    assert np.max(np.abs(a - b)) <= 1e-12
+
+
+@pytest.mark.slow
+def test_fp32_drift_against_fp64_at_256():
+    """The FP32 scheme stays within 1e-5 * max(psi) of FP64 on the 256^3 sine workload."""
+    p = inputs.smooth_sine(256, dtype=np.float64)
+    a = oracle.fmm(p.F, p.h, p.sources)
+    b = oracle.fmm(p.F.astype(np.float32), p.h, p.sources, dtype=np.float32)
+    assert np.max(np.abs(b - a)) <= 1e-5 * np.max(a)
+
+
+# ----------------------------------------------------------------------- stride network
+def test_mlp_gradient_finite_differences():
+    rng = np.random.default_rng(0)
+    P = rng.normal(0, 0.3, size=oracle.MLP_NPARAMS)
+    X = rng.normal(0, 1, size=(7, 12))
+    T = rng.uniform(np.log(0.25), np.log(8.0), size=7)
+    loss, g = oracle.mlp_loss_grad(P, X, T)
+    eps = 1e-6
+    idx = rng.choice(oracle.MLP_NPARAMS, size=60, replace=False)
+    idx = np.concatenate([idx, [0, 383, 384, 415, 416, 1439, 1440, 1471, 1472, 1503, 1504]])
+    for i in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += eps
+        Pm[i] -= eps
+        fd = (oracle.mlp_loss_grad(Pp, X, T)[0] - oracle.mlp_loss_grad(Pm, X, T)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8, (i, fd, g[i])
+    y = oracle.mlp_forward(P, X)
+    assert np.all((y >= np.log(0.25) - 1e-12) & (y <= np.log(8.0) + 1e-12))
+    assert loss == pytest.approx(np.mean((y - T) ** 2), rel=1e-12)
+
+
+def test_adam_step_matches_closed_form_first_step():
+    """First Adam step moves each parameter by lr * sign(g) (bias-corrected moments)."""
+    P = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    m, v = np.zeros(3), np.zeros(3)
+    oracle.adam_step(P, g, m, v, 0.01, 0.9, 0.999, 1e-12, 1)
+    assert np.allclose(P, [1.0 - 0.01, -2.0 + 0.01, 0.5 - 0.01], rtol=0, atol=1e-9)
