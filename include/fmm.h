@@ -1,0 +1,232 @@
+/*
+ * fmm.h -- C ABI of the MI355X (gfx950) block-based restarted narrow-band
+ * fast marching library.
+ *
+ * The library solves the eikonal boundary-value problem |grad psi| F = 1 with
+ * psi = psi0 on a set of source points (Yang 2018, Eq. (1)), discretised by
+ * the first-order Godunov upwind scheme on a uniform grid (Eq. (2)-(3)), with
+ * the block-based method of the paper: the grid is cut into B^3 blocks padded
+ * by one ghost layer (Sec. 2.3), each block marches its own narrow band up to
+ * a global bound that rises by a stride at every restart (Sec. 2.4, Alg. 4,
+ * Alg. 6), blocks then exchange ghost faces (Alg. 5), and activation flags
+ * skip idle blocks in both steps (Sec. 2.5, 2.6).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Grid layout: linear index of point (i, j, k) is i + nx*(j + ny*k), i.e.
+ *    a C-contiguous array of shape (nz, ny, nx).  Grid spacing h in all three
+ *    directions.
+ *  * Buffers named *_dev are device memory owned by the caller (for example
+ *    torch tensors); the library never frees them.  Host arrays are read
+ *    during the call only and may be freed when it returns.
+ *  * Precision: FMM_F32 means F and psi are float, FMM_F64 means double.  The
+ *    solver computes in that precision; the restart bound is kept in double.
+ *  * Streams: work is queued on hip_stream (a hipStream_t; NULL = the null
+ *    stream).  Every solve entry point returns after the result is complete,
+ *    unless noted.
+ *  * Errors: every int-returning function returns FMM_OK (0) or a negative
+ *    FMM_E* code; fmm_strerror() gives text, fmm_last_error_detail() the
+ *    message of the last failure on the calling thread.  No C++ exception
+ *    crosses this boundary.
+ *  * Library workspace (blocked tiles, bands, flags, lists) is allocated by the
+ *    library from a per-device cache and reused across calls.
+ *  * Calls are thread-compatible, not thread-safe: do not run two solves on the
+ *    same device at once from different threads.
+ */
+#ifndef FMM_H
+#define FMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_OK 0
+#define FMM_EINVAL (-1)   /* invalid argument                                   */
+#define FMM_ENOMEM (-2)   /* device or host allocation failed                   */
+#define FMM_EHIP (-3)     /* HIP runtime error; see fmm_last_error_detail()     */
+#define FMM_ENOCONV (-4)  /* restart cap reached, or a device watchdog fired    */
+#define FMM_ENOTSUP (-5)  /* unsupported combination (block size, launch mode)  */
+
+typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
+
+/* Stride policy of the restart driver. */
+typedef enum {
+    FMM_STRIDE_FIXED = 0,   /* bound_r = min(r * stride, width)            (Alg. 6) */
+    FMM_STRIDE_LEARNED = 1  /* bound_r = bound_{r-1} + m_r * stride, m_r from the
+                               stride network evaluated on the device at the end
+                               of restart r-1; falls back to m_r = 1 when the
+                               weights are absent or the output is not finite */
+} fmm_stride_mode;
+
+/* Launch strategy of the restart loop. */
+typedef enum {
+    FMM_LAUNCH_PERSISTENT = 0, /* one cooperative persistent kernel runs every restart */
+    FMM_LAUNCH_HOST = 1        /* one march and one exchange kernel per restart,
+                                  driven from the host (diagnostic)                 */
+} fmm_launch_mode;
+
+/* A point of Gamma (Alg. 1): grid index and its value psi0 >= 0. */
+typedef struct {
+    int64_t i, j, k;
+    double psi0;
+} fmm_source;
+
+/* Optional knobs; fmm_options_default() fills the defaults noted here. */
+typedef struct {
+    double width;             /* width_band of Alg. 4 / Alg. 5; +inf (default) = full solve */
+    int32_t stride_mode;      /* fmm_stride_mode, default FIXED                               */
+    const void *mlp_weights;  /* device pointer to FMM_MLP_BLOB_FLOATS floats (see below);
+                                 NULL = fixed stride                                         */
+    int32_t waves_per_block;  /* 64-lane waves cooperating on one block: 1, 2 or 4; 0 = 1     */
+    int32_t launch_mode;      /* fmm_launch_mode, default PERSISTENT                          */
+    int64_t max_restarts;     /* watchdog; 0 = default (1e7)                                  */
+    int32_t grid_limit;       /* persistent workgroups cap; 0 = occupancy-derived              */
+    void *trace_dev;          /* nullable device buffer of trace_cap fmm_trace_row             */
+    int32_t trace_cap;        /* rows available in trace_dev                                   */
+} fmm_options;
+
+/* Solve statistics (host struct, filled after the call). */
+typedef struct {
+    int64_t restarts;          /* iterations of the loop of Alg. 6                          */
+    int64_t pops;              /* Remove_Min events over all blocks (ghost points included) */
+    int64_t march_calls;       /* March_Narrow_Band calls (blocks with A = TRUE)            */
+    int64_t exchange_calls;    /* Integrate_Ghost_Cell_Data calls (blocks with any C)       */
+    int64_t tile_loads;        /* march calls that had work below the bound                 */
+    double final_bound;        /* bound of the last restart                                 */
+    double elapsed_ms;         /* device time from the first to the last kernel             */
+    int32_t grid;              /* persistent workgroups used (0 in host mode)               */
+    int32_t block;             /* block edge B used                                        */
+    int32_t waves_per_block;   /* waves per block used                                     */
+    int32_t reserved;
+} fmm_stats;
+
+/* One row per restart, written when fmm_options.trace_dev is given:
+   the inputs of the stride network and what the restart cost. */
+#define FMM_NFEAT 12
+typedef struct {
+    float feat[FMM_NFEAT];   /* raw features at the end of the restart (see fmm_mlp_*)   */
+    double bound;            /* bound of this restart                                     */
+    double stride_used;      /* bound - previous bound                                    */
+    int64_t pops;            /* Remove_Min events in this restart                          */
+    int64_t t_start;         /* device wall clock (100 MHz) at the start of the restart    */
+    int64_t t_end;           /* and at its end                                             */
+    int32_t active;          /* blocks in the march list of this restart                   */
+    int32_t next_active;     /* blocks in the march list of the next restart               */
+} fmm_trace_row;
+
+void fmm_options_default(fmm_options *opt);
+
+/*
+ * Solve one problem (the main procedure of Alg. 6 with Alg. 1-5).
+ *
+ *   nx, ny, nz   grid points per axis (> 0, each divisible by block)
+ *   h            grid spacing (> 0, finite)
+ *   dtype        FMM_F32 or FMM_F64: element type of F_dev and psi_dev
+ *   F_dev        speed F >= 0 at every point, nx*ny*nz elements; F = 0 marks an
+ *                obstacle where the quadratic is never solved (paper Sec. 3.3)
+ *   src, nsrc    host array of nsrc >= 1 points of Gamma, each inside the grid,
+ *                psi0 >= 0 finite; a repeated point keeps the smallest psi0
+ *   block        block edge B: 4, 8 or 16 (the paper's dimBlock)
+ *   stride       restart stride (> 0, +inf allowed = the non-restarted block
+ *                method of Sec. 2.3)
+ *   psi_dev      output, nx*ny*nz elements; points never reached are +inf
+ *   hip_stream   stream to queue on
+ *   opt          nullable: defaults
+ *   stats        nullable: filled on success
+ */
+int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
+              const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
+              void *hip_stream, const fmm_options *opt, fmm_stats *stats);
+
+/* One problem of a batch (same meaning as the fmm_solve arguments).
+   The stride of each problem is its own; dtype must be the same across a batch. */
+typedef struct {
+    int64_t nx, ny, nz;
+    double h;
+    const void *F_dev;
+    void *psi_dev;
+    const fmm_source *src;
+    int32_t nsrc;
+    double stride;
+} fmm_problem;
+
+/*
+ * Solve nsolves independent problems in ONE persistent launch: the blocks of
+ * every problem share the march and exchange lists of Alg. 6, and each problem
+ * keeps its own bound (r * its stride).  block and waves_per_block apply to the
+ * whole batch (fmm_autotune chooses them).  per_solve_stats is nullable or an
+ * array of nsolves; restarts are per problem, elapsed_ms is the batch time.
+ */
+int fmm_solve_batched(int32_t nsolves, const fmm_problem *problems, int32_t dtype, int32_t block,
+                      const fmm_options *opt, void *hip_stream, fmm_stats *per_solve_stats);
+
+/* Autotuner result. */
+typedef struct {
+    int32_t block;
+    int32_t waves_per_block;
+    double ms;               /* measured time of the winning configuration */
+} fmm_tuning;
+
+/*
+ * Choose block edge and waves per block for a batch by timing every supported
+ * pair (block in {8, 16} dividing all sides, waves in {1, 2, 4}) on the given
+ * sample problems, once each after one warm-up.  Results are cached in memory
+ * and, when cache_path is not NULL, in a small text file keyed by device name,
+ * dtype and a size bin, so a later call with the same key does not time again.
+ * psi_dev of the sample problems is overwritten.
+ */
+int fmm_autotune(int32_t nsamples, const fmm_problem *samples, int32_t dtype,
+                 const char *cache_path, void *hip_stream, fmm_tuning *out);
+
+/* ---------------------------------------------------------------- stride network
+ * A 12-32-32-1 perceptron (ReLU hidden layers) maps standardised restart
+ * features to log m = ln(1/4) + sigmoid(z) * ln(32), m in [1/4, 8]; the next
+ * stride is m times the base stride.  Parameters (1505 floats), row-major
+ * out x in: W1[32][12], b1[32], W2[32][32], b2[32], W3[1][32], b3[1].
+ * The device blob given to fmm_options.mlp_weights holds the 1505 parameters
+ * followed by the 12 feature means and the 12 feature standard deviations.
+ *
+ * Features (raw, in this order): bound / (n h), active-block fraction, the
+ * fractions of active blocks whose band size falls in the bins {0}, [1,3],
+ * [4,15], [16,63], [64,255], [256,1023], [1024,4095], [4096,inf), the restart
+ * index / n, and the mean speed over active blocks; n is the largest grid side.
+ */
+#define FMM_MLP_NPARAMS 1505
+#define FMM_MLP_BLOB_FLOATS (FMM_MLP_NPARAMS + 2 * FMM_NFEAT)
+
+/* y_dev[s] = predicted log multiplier for standardised features x_dev[s][12].
+   params_dev: 1505 floats.  Device buffers, FP32. */
+int fmm_mlp_forward(const float *params_dev, const float *x_dev, int64_t n, float *y_dev,
+                    void *hip_stream);
+
+/* loss (device scalar) = mean_s (y_s - t_s)^2 and its gradient (1505 floats). */
+int fmm_mlp_loss_grad(const float *params_dev, const float *x_dev, const float *t_dev, int64_t n,
+                      float *loss_dev, float *grad_dev, void *hip_stream);
+
+/* One Adam step (Kingma & Ba 2015) at iteration t >= 1 on 1505 parameters;
+   m_dev and v_dev are the moment buffers, updated in place. */
+int fmm_mlp_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, float lr,
+                 float beta1, float beta2, float eps, int64_t t, void *hip_stream);
+
+/* Train for `steps` full-batch Adam steps from the parameters in params_dev
+   (updated in place).  loss_hist_dev (nullable) receives one float per step. */
+int fmm_mlp_train(float *params_dev, const float *x_dev, const float *t_dev, int64_t n,
+                  int64_t steps, float lr, float *loss_hist_dev, void *hip_stream);
+
+/* ---------------------------------------------------------------- diagnostics */
+/* Each 64-lane wave w writes the minimum of in_dev[64w .. 64w+63] to out_dev[w],
+   using the same cross-lane reduction as the march's argmin. */
+int fmm_selftest_wave_min(const uint32_t *in_dev, uint32_t *out_dev, int32_t nwaves,
+                          void *hip_stream);
+
+const char *fmm_strerror(int code);
+const char *fmm_last_error_detail(void);
+/* Library version string. */
+const char *fmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H */

@@ -1,0 +1,34 @@
+"""Build the HIP library (libfmm_hip.so) in-tree for gfx950 with hipcc.
+
+Flags: -O3; no floating-point contraction, correctly rounded FP32 divide and
+square root (the solver's arithmetic rounds exactly as written); packed FP32
+instructions disabled.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libfmm_hip.so")
+SOURCES = ["fmm_host.hip", "fmm_mlp.hip", "fmm_tune.hip"]
+ARCH = os.environ.get("FMM_OFFLOAD_ARCH", "gfx950")
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+           "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+           "-I", os.path.join(os.path.dirname(HERE), "include"),
+           "-o", LIB + ".tmp"] + srcs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose="-v" in sys.argv)

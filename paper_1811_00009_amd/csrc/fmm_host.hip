@@ -1,0 +1,679 @@
+// fmm_host.hip -- host side of the C ABI declared in include/fmm.h: argument
+// validation, the per-device workspace cache, source set-up (Alg. 1), kernel
+// dispatch over (precision, block edge, waves per block), the persistent and
+// host-driven restart loops (Alg. 6), statistics, the autotuner and the
+// diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fmm.h"
+#include "fmm_kernels.hpp"
+
+using namespace fmmdev;
+
+static_assert(sizeof(TraceRow) == sizeof(fmm_trace_row), "trace row layout");
+
+namespace {
+
+thread_local std::string g_detail;
+
+int fail(int code, const std::string &msg)
+{
+    g_detail = msg;
+    return code;
+}
+
+} // namespace
+
+// Used by the stride-network kernels to report through fmm_last_error_detail().
+void fmm_internal_set_detail(const std::string &msg) { g_detail = msg; }
+
+namespace {
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(e_ == hipErrorOutOfMemory ? FMM_ENOMEM : FMM_EHIP,                     \
+                        std::string(#x) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+int ensure(DevBuf &b, size_t bytes, const char *what)
+{
+    if (bytes == 0) bytes = 16;
+    if (b.p && b.cap >= bytes) return 0;
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(FMM_ENOMEM, std::string("allocating ") + what + " (" +
+                                    std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+    }
+    b.cap = bytes;
+    return 0;
+}
+
+// Library-owned device memory of one GPU, grown on demand and kept for reuse.
+struct Workspace {
+    DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, list0, list1, ctl, prob, src,
+        plastr, ppops;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, Workspace> g_ws;
+
+struct Device {
+    int id = 0;
+    int cus = 0;
+    int64_t ticks_per_s = 100000000;
+    int coop = 0;
+    std::string name;
+};
+
+int device_info(Device &d)
+{
+    HIPCHK(hipGetDevice(&d.id));
+    HIPCHK(hipDeviceGetAttribute(&d.cus, hipDeviceAttributeMultiprocessorCount, d.id));
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d.id) == hipSuccess && khz > 0)
+        d.ticks_per_s = (int64_t)khz * 1000;
+    HIPCHK(hipDeviceGetAttribute(&d.coop, hipDeviceAttributeCooperativeLaunch, d.id));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, d.id));
+    d.name = prop.gcnArchName;
+    return 0;
+}
+
+// A problem after validation, with its sources in library form.
+struct Prob {
+    ProbDesc d;
+    std::vector<fmm_source> src;
+};
+
+int validate_problem(int64_t nx, int64_t ny, int64_t nz, double h, const void *F, void *psi,
+                     const fmm_source *src, int32_t nsrc, int32_t block, double stride,
+                     const std::string &who)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(FMM_EINVAL, who + ": grid dimensions must be > 0");
+    if (!(h > 0) || !std::isfinite(h)) return fail(FMM_EINVAL, who + ": h must be finite and > 0");
+    if (!(stride > 0)) return fail(FMM_EINVAL, who + ": stride must be > 0 (inf allowed)");
+    if (block != 4 && block != 8 && block != 16)
+        return fail(FMM_ENOTSUP, who + ": block must be 4, 8 or 16");
+    if (nx % block || ny % block || nz % block)
+        return fail(FMM_EINVAL, who + ": every grid dimension must be divisible by block");
+    if (nx * ny * nz > ((int64_t)1 << 34)) return fail(FMM_EINVAL, who + ": grid too large");
+    if (!F || !psi) return fail(FMM_EINVAL, who + ": NULL F or psi buffer");
+    if (!src || nsrc <= 0) return fail(FMM_EINVAL, who + ": at least one source is required");
+    for (int32_t s = 0; s < nsrc; ++s) {
+        const fmm_source &p = src[s];
+        if (p.i < 0 || p.j < 0 || p.k < 0 || p.i >= nx || p.j >= ny || p.k >= nz)
+            return fail(FMM_EINVAL, who + ": source " + std::to_string(s) + " outside the grid");
+        if (!(p.psi0 >= 0) || !std::isfinite(p.psi0))
+            return fail(FMM_EINVAL, who + ": source value must be finite and >= 0");
+    }
+    return 0;
+}
+
+// Alg. 1, points of Gamma: every padded block (interior or ghost face, not
+// ghost edges/corners) holding a source point gets an entry; repeated points
+// keep the smallest value.
+void build_sources(const std::vector<Prob> &probs, int B, std::vector<SrcEntry> &out,
+                   std::vector<int32_t> &first_list)
+{
+    std::map<std::pair<int64_t, int32_t>, double> ent;
+    const int P = B + 2;
+    for (const Prob &pb : probs) {
+        const ProbDesc &d = pb.d;
+        for (const fmm_source &s : pb.src) {
+            for (int64_t bz = s.k / B - 1; bz <= s.k / B + 1; ++bz)
+                for (int64_t by = s.j / B - 1; by <= s.j / B + 1; ++by)
+                    for (int64_t bx = s.i / B - 1; bx <= s.i / B + 1; ++bx) {
+                        if (bx < 0 || by < 0 || bz < 0 || bx >= d.mx || by >= d.my || bz >= d.mz)
+                            continue;
+                        const int64_t li = s.i - bx * B + 1, lj = s.j - by * B + 1,
+                                      lk = s.k - bz * B + 1;
+                        if (li < 0 || lj < 0 || lk < 0 || li > B + 1 || lj > B + 1 || lk > B + 1)
+                            continue;
+                        const int ng = (li == 0 || li == B + 1) + (lj == 0 || lj == B + 1) +
+                                       (lk == 0 || lk == B + 1);
+                        if (ng > 1) continue;
+                        const int64_t ib = d.blk0 + bx + (int64_t)d.mx * (by + (int64_t)d.my * bz);
+                        const int32_t t = (int32_t)(li + P * (lj + P * lk));
+                        const double v = s.psi0 + 0.0;  // -0 -> +0
+                        auto key = std::make_pair(ib, t);
+                        auto it = ent.find(key);
+                        if (it == ent.end() || v < it->second) ent[key] = v;
+                    }
+        }
+    }
+    out.clear();
+    first_list.clear();
+    for (auto &kv : ent) {
+        SrcEntry e{};
+        e.ib = kv.first.first;
+        e.t = kv.first.second;
+        e.v = kv.second;
+        out.push_back(e);
+        if (first_list.empty() || first_list.back() != (int32_t)e.ib) first_list.push_back((int32_t)e.ib);
+    }
+}
+
+template <typename R>
+__global__ void k_fill_blkprob(int32_t *bp, const ProbDesc *prob, int32_t nprob, int64_t nblk)
+{
+    for (int64_t ib = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; ib < nblk;
+         ib += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nprob - 1;
+        while (lo < hi) {  // last problem with blk0 <= ib
+            int mid = (lo + hi + 1) / 2;
+            if (prob[mid].blk0 <= ib) lo = mid;
+            else hi = mid - 1;
+        }
+        bp[ib] = lo;
+    }
+}
+
+int map_device_error(int code)
+{
+    switch (code) {
+    case 0: return 0;
+    case kErrBadSpeed: return fail(FMM_EINVAL, "speed F has a negative, NaN or infinite value");
+    case kErrPopCap: return fail(FMM_ENOCONV, "device watchdog: a march call exceeded the pop cap");
+    case kErrTimeout: return fail(FMM_ENOCONV, "device watchdog: a grid barrier wait timed out");
+    case kErrRestarts: return fail(FMM_ENOCONV, "restart cap reached");
+    default: return fail(FMM_EHIP, "unknown device error " + std::to_string(code));
+    }
+}
+
+struct RunOut {
+    Ctl ctl;
+    float ms;
+    int grid;
+    std::vector<int32_t> lastr;
+    std::vector<unsigned long long> ppops;
+};
+
+template <typename R, int B, int W>
+int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, RunOut &out)
+{
+    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3;
+    using L = Lds<R, B, W>;
+    Device dev;
+    if (int rc = device_info(dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace &ws = g_ws[dev.id];
+
+    // block ranges of the problems in the pooled arrays
+    int64_t nblk = 0;
+    for (Prob &pb : probs) {
+        ProbDesc &d = pb.d;
+        d.mx = d.nx / B;
+        d.my = d.ny / B;
+        d.mz = d.nz / B;
+        d.blk0 = nblk;
+        d.nblk = (int64_t)d.mx * d.my * d.mz;
+        d.nmax = std::max(d.nx, std::max(d.ny, d.nz));
+        nblk += d.nblk;
+    }
+    if (nblk >= ((int64_t)1 << 31)) return fail(FMM_EINVAL, "too many blocks");
+    const int32_t nprob = (int32_t)probs.size();
+
+    int rc = 0;
+    if ((rc = ensure(ws.psi, (size_t)nblk * T * sizeof(R), "psi tiles")) ||
+        (rc = ensure(ws.tag, (size_t)nblk * T, "tag tiles")) ||
+        (rc = ensure(ws.band, (size_t)nblk * T * 2, "band arrays")) ||
+        (rc = ensure(ws.bandn, (size_t)nblk * 4, "band sizes")) ||
+        (rc = ensure(ws.rhs, (size_t)nblk * B3 * sizeof(R), "rhs tiles")) ||
+        (rc = ensure(ws.bmin, (size_t)nblk * sizeof(R), "band minima")) ||
+        (rc = ensure(ws.A, (size_t)nblk, "activation flags")) ||
+        (rc = ensure(ws.Cm, (size_t)nblk * 4, "exchange flags")) ||
+        (rc = ensure(ws.bprob, (size_t)nblk * 4, "block problems")) ||
+        (rc = ensure(ws.fmean, (size_t)nblk * 4, "block speeds")) ||
+        (rc = ensure(ws.list0, (size_t)nblk * 4, "march list 0")) ||
+        (rc = ensure(ws.list1, (size_t)nblk * 4, "march list 1")) ||
+        (rc = ensure(ws.ctl, sizeof(Ctl), "control block")) ||
+        (rc = ensure(ws.prob, sizeof(ProbDesc) * nprob, "problem table")) ||
+        (rc = ensure(ws.plastr, sizeof(int32_t) * nprob, "problem restarts")) ||
+        (rc = ensure(ws.ppops, sizeof(unsigned long long) * nprob, "problem pops")))
+        return rc;
+    if (!ws.e0) {
+        HIPCHK(hipEventCreate(&ws.e0));
+        HIPCHK(hipEventCreate(&ws.e1));
+    }
+
+    std::vector<SrcEntry> ents;
+    std::vector<int32_t> first;
+    build_sources(probs, B, ents, first);
+    if ((rc = ensure(ws.src, sizeof(SrcEntry) * std::max<size_t>(1, ents.size()), "sources")))
+        return rc;
+
+    std::vector<ProbDesc> descs(nprob);
+    for (int32_t q = 0; q < nprob; ++q) descs[q] = probs[q].d;
+    Ctl hc;
+    std::memset(&hc, 0, sizeof(hc));
+    hc.n_list[1] = (int)first.size();  // restart 1 marches list[1]
+
+    HIPCHK(hipMemcpyAsync(ws.prob.p, descs.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.src.p, ents.data(), sizeof(SrcEntry) * ents.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.list1.p, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.ctl.p, &hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(ws.plastr.p, 0, sizeof(int32_t) * nprob, st));
+    HIPCHK(hipMemsetAsync(ws.ppops.p, 0, sizeof(unsigned long long) * nprob, st));
+
+    KParams<R> kp{};
+    kp.psi_t = (R *)ws.psi.p;
+    kp.tag_t = (uint8_t *)ws.tag.p;
+    kp.band_t = (uint16_t *)ws.band.p;
+    kp.band_n = (int32_t *)ws.bandn.p;
+    kp.rhs_t = (R *)ws.rhs.p;
+    kp.bmin = (R *)ws.bmin.p;
+    kp.A = (uint8_t *)ws.A.p;
+    kp.Cm = (uint32_t *)ws.Cm.p;
+    kp.blk_prob = (int32_t *)ws.bprob.p;
+    kp.fmean = (float *)ws.fmean.p;
+    kp.list0 = (int32_t *)ws.list0.p;
+    kp.list1 = (int32_t *)ws.list1.p;
+    kp.ctl = (Ctl *)ws.ctl.p;
+    kp.prob = (const ProbDesc *)ws.prob.p;
+    kp.nprob = nprob;
+    kp.stride_mode = o.stride_mode == FMM_STRIDE_LEARNED ? 1 : 0;
+    kp.nblk = nblk;
+    kp.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000000;
+    kp.pop_cap = (int64_t)64 * T;
+    kp.timeout_ticks = dev.ticks_per_s * 10;
+    kp.mlp = (const float *)o.mlp_weights;
+    kp.trace = o.trace_dev;
+    kp.trace_cap = o.trace_dev ? o.trace_cap : 0;
+    kp.want_features = (kp.trace_cap > 0 || kp.stride_mode) ? 1 : 0;
+    kp.prob_lastr = (int32_t *)ws.plastr.p;
+    kp.prob_pops = (unsigned long long *)ws.ppops.p;
+
+    const size_t lds = L::bytes;
+    HIPCHK(hipEventRecord(ws.e0, st));
+    k_fill_blkprob<R><<<(unsigned)std::min<int64_t>((nblk + 255) / 256, 4096), 256, 0, st>>>(
+        kp.blk_prob, kp.prob, nprob, nblk);
+    k_init<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
+    if (!ents.empty())
+        k_sources<R><<<(unsigned)((ents.size() + 127) / 128), 128, 0, st>>>(
+            kp, (const SrcEntry *)ws.src.p, (int32_t)ents.size(), T);
+    HIPCHK(hipGetLastError());
+
+    int per_cu = 0;
+    int grid = 0;
+    if (o.launch_mode == FMM_LAUNCH_PERSISTENT) {
+        auto kern = k_persistent<R, B, W>;
+        HIPCHK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, lds));
+        if (per_cu <= 0) return fail(FMM_ENOTSUP, "persistent kernel does not fit on a compute unit");
+        if (!dev.coop) return fail(FMM_ENOTSUP, "device lacks cooperative launch");
+        int64_t g = (int64_t)per_cu * dev.cus;
+        g = std::min<int64_t>(g, nblk);
+        if (o.grid_limit > 0) g = std::min<int64_t>(g, o.grid_limit);
+        grid = (int)std::max<int64_t>(g, 1);
+        void *args[] = {&kp};
+        HIPCHK(hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(64 * W), args, lds, st));
+    } else {
+        if (kp.stride_mode) return fail(FMM_ENOTSUP, "learned stride needs the persistent launch");
+        auto km = k_march<R, B, W>;
+        auto kx = k_exchange<R, B, W>;
+        HIPCHK(hipFuncSetAttribute((const void *)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        HIPCHK(hipFuncSetAttribute((const void *)kx, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, km, 64 * W, lds));
+        const int64_t cap = std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * dev.cus);
+        int ncur = (int)first.size();
+        Ctl *dctl = (Ctl *)ws.ctl.p;
+        int64_t r = 1;
+        for (;; ++r) {
+            const int c = (int)(r & 1);
+            k_restart_prologue<R><<<1, 1, 0, st>>>(kp, r);
+            const int gm = (int)std::max<int64_t>(1, std::min<int64_t>(ncur, cap));
+            km<<<gm, 64 * W, lds, st>>>(kp, r);
+            const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(nblk, cap));
+            kx<<<gx, 64 * W, lds, st>>>(kp, r);
+            HIPCHK(hipGetLastError());
+            int nn = 0, ab = 0;
+            HIPCHK(hipMemcpyAsync(&nn, &dctl->n_list[c ^ 1], sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&ab, &dctl->abort, sizeof(int), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (ab) break;
+            ncur = nn;
+            if (nn == 0) break;
+            if (r >= kp.max_restarts) {
+                int code = kErrRestarts;
+                HIPCHK(hipMemcpyAsync(&dctl->abort, &code, sizeof(int), hipMemcpyHostToDevice, st));
+                break;
+            }
+        }
+        const double fb = std::min((double)r * probs[0].d.stride, probs[0].d.width);
+        long long rr = r;
+        HIPCHK(hipMemcpyAsync(&dctl->restarts, &rr, sizeof(rr), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(&dctl->final_bound, &fb, sizeof(fb), hipMemcpyHostToDevice, st));
+    }
+    k_unlayout<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(ws.e1, st));
+    HIPCHK(hipMemcpyAsync(&out.ctl, ws.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    out.lastr.resize(nprob);
+    out.ppops.resize(nprob);
+    HIPCHK(hipMemcpyAsync(out.lastr.data(), ws.plastr.p, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(out.ppops.data(), ws.ppops.p, sizeof(unsigned long long) * nprob, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipEventElapsedTime(&out.ms, ws.e0, ws.e1));
+    out.grid = grid;
+    return map_device_error(out.ctl.abort);
+}
+
+using RunFn = int (*)(std::vector<Prob> &, const fmm_options &, hipStream_t, RunOut &);
+
+template <typename R>
+RunFn pick(int B, int W)
+{
+#define FMM_CASE(b, w) \
+    if (B == b && W == w) return &run_solve<R, b, w>;
+    FMM_CASE(4, 1)
+    FMM_CASE(4, 2)
+    FMM_CASE(4, 4)
+    FMM_CASE(8, 1)
+    FMM_CASE(8, 2)
+    FMM_CASE(8, 4)
+    FMM_CASE(16, 1)
+    FMM_CASE(16, 2)
+    FMM_CASE(16, 4)
+#undef FMM_CASE
+    return nullptr;
+}
+
+int dispatch(int dtype, int B, const fmm_options &o, std::vector<Prob> &probs, hipStream_t st, RunOut &out)
+{
+    const int W = o.waves_per_block <= 0 ? 1 : o.waves_per_block;
+    if (W != 1 && W != 2 && W != 4) return fail(FMM_EINVAL, "waves_per_block must be 1, 2 or 4");
+    RunFn fn = nullptr;
+    if (dtype == FMM_F32) fn = pick<float>(B, W);
+    else if (dtype == FMM_F64) fn = pick<double>(B, W);
+    else return fail(FMM_EINVAL, "dtype must be FMM_F32 or FMM_F64");
+    if (!fn) return fail(FMM_ENOTSUP, "unsupported block / waves combination");
+    return fn(probs, o, st, out);
+}
+
+int check_options(const fmm_options &o)
+{
+    if (!(o.width > 0)) return fail(FMM_EINVAL, "width must be > 0");
+    if (o.stride_mode != FMM_STRIDE_FIXED && o.stride_mode != FMM_STRIDE_LEARNED)
+        return fail(FMM_EINVAL, "unknown stride_mode");
+    if (o.launch_mode != FMM_LAUNCH_PERSISTENT && o.launch_mode != FMM_LAUNCH_HOST)
+        return fail(FMM_EINVAL, "unknown launch_mode");
+    if (o.trace_dev && o.trace_cap < 0) return fail(FMM_EINVAL, "trace_cap must be >= 0");
+    if (o.max_restarts < 0) return fail(FMM_EINVAL, "max_restarts must be >= 0");
+    return 0;
+}
+
+void fill_stats(fmm_stats *s, const RunOut &r, int B, int W, int64_t restarts, int64_t pops)
+{
+    std::memset(s, 0, sizeof(*s));
+    s->restarts = restarts;
+    s->pops = pops;
+    s->march_calls = (int64_t)r.ctl.march_calls;
+    s->exchange_calls = (int64_t)r.ctl.exchange_calls;
+    s->tile_loads = (int64_t)r.ctl.tile_loads;
+    s->final_bound = r.ctl.final_bound;
+    s->elapsed_ms = r.ms;
+    s->grid = r.grid;
+    s->block = B;
+    s->waves_per_block = W;
+}
+
+int build_batch(int32_t nsolves, const fmm_problem *problems, int32_t block, double width,
+                const char *who, std::vector<Prob> &probs)
+{
+    probs.assign(nsolves, Prob{});
+    for (int32_t q = 0; q < nsolves; ++q) {
+        const fmm_problem &p = problems[q];
+        if (int rc = validate_problem(p.nx, p.ny, p.nz, p.h, p.F_dev, p.psi_dev, p.src, p.nsrc, block,
+                                      p.stride, std::string(who) + "[" + std::to_string(q) + "]"))
+            return rc;
+        ProbDesc &d = probs[q].d;
+        std::memset(&d, 0, sizeof(d));
+        d.F = p.F_dev;
+        d.psi = p.psi_dev;
+        d.nx = (int32_t)p.nx;
+        d.ny = (int32_t)p.ny;
+        d.nz = (int32_t)p.nz;
+        d.h = p.h;
+        d.stride = p.stride;
+        d.width = width;
+        probs[q].src.assign(p.src, p.src + p.nsrc);
+    }
+    return 0;
+}
+
+// Autotuner cache: key -> (block, waves, ms), in memory and optionally in a text file.
+std::map<std::string, fmm_tuning> g_tune_cache;
+
+std::string tune_key(const std::string &arch, int32_t dtype, int32_t nsamples, const fmm_problem *s)
+{
+    double pts = 0;
+    int64_t smin = INT64_MAX, smax = 0;
+    for (int32_t q = 0; q < nsamples; ++q) {
+        pts += (double)s[q].nx * s[q].ny * s[q].nz;
+        smin = std::min<int64_t>(smin, std::min(s[q].nx, std::min(s[q].ny, s[q].nz)));
+        smax = std::max<int64_t>(smax, std::max(s[q].nx, std::max(s[q].ny, s[q].nz)));
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s:%s:n%d:pts2^%d:side%lld-%lld", arch.c_str(),
+                  dtype == FMM_F32 ? "f32" : "f64", (int)nsamples, (int)std::floor(std::log2(std::max(pts, 1.0))),
+                  (long long)smin, (long long)smax);
+    return buf;
+}
+
+bool tune_file_lookup(const char *path, const std::string &key, fmm_tuning &t)
+{
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char k[256];
+    int b, w;
+    double ms;
+    bool found = false;
+    while (std::fscanf(f, "%255s %d %d %lf", k, &b, &w, &ms) == 4) {
+        if (key == k) {
+            t.block = b;
+            t.waves_per_block = w;
+            t.ms = ms;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_file_store(const char *path, const std::string &key, const fmm_tuning &t)
+{
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), t.block, t.waves_per_block, t.ms);
+    std::fclose(f);
+}
+
+} // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+void fmm_options_default(fmm_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->width = INFINITY;
+    opt->stride_mode = FMM_STRIDE_FIXED;
+    opt->waves_per_block = 1;
+    opt->launch_mode = FMM_LAUNCH_PERSISTENT;
+}
+
+int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
+              const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
+              void *hip_stream, const fmm_options *opt, fmm_stats *stats)
+{
+    try {
+        fmm_options o;
+        fmm_options_default(&o);
+        if (opt) o = *opt;
+        if (int rc = check_options(o)) return rc;
+        if (int rc = validate_problem(nx, ny, nz, h, F_dev, psi_dev, src, nsrc, block, stride, "fmm_solve"))
+            return rc;
+        if (o.stride_mode == FMM_STRIDE_LEARNED && !std::isfinite(stride))
+            return fail(FMM_EINVAL, "learned stride needs a finite base stride");
+        std::vector<Prob> probs(1);
+        ProbDesc &d = probs[0].d;
+        std::memset(&d, 0, sizeof(d));
+        d.F = F_dev;
+        d.psi = psi_dev;
+        d.nx = (int32_t)nx;
+        d.ny = (int32_t)ny;
+        d.nz = (int32_t)nz;
+        d.h = h;
+        d.stride = stride;
+        d.width = o.width;
+        probs[0].src.assign(src, src + nsrc);
+        RunOut out{};
+        int rc = dispatch(dtype, block, o, probs, (hipStream_t)hip_stream, out);
+        if (stats && (rc == 0 || rc == FMM_ENOCONV))
+            fill_stats(stats, out, block, o.waves_per_block <= 0 ? 1 : o.waves_per_block,
+                       out.ctl.restarts, (int64_t)out.ctl.pops);
+        return rc;
+    } catch (const std::exception &e) {
+        return fail(FMM_EHIP, std::string("fmm_solve: ") + e.what());
+    } catch (...) {
+        return fail(FMM_EHIP, "fmm_solve: unknown exception");
+    }
+}
+
+int fmm_solve_batched(int32_t nsolves, const fmm_problem *problems, int32_t dtype, int32_t block,
+                      const fmm_options *opt, void *hip_stream, fmm_stats *per_solve_stats)
+{
+    try {
+        if (nsolves <= 0 || !problems) return fail(FMM_EINVAL, "fmm_solve_batched: no problems");
+        fmm_options o;
+        fmm_options_default(&o);
+        if (opt) o = *opt;
+        if (int rc = check_options(o)) return rc;
+        if (o.stride_mode != FMM_STRIDE_FIXED)
+            return fail(FMM_ENOTSUP, "fmm_solve_batched: fixed stride only");
+        if (o.launch_mode != FMM_LAUNCH_PERSISTENT)
+            return fail(FMM_ENOTSUP, "fmm_solve_batched: persistent launch only");
+        std::vector<Prob> probs;
+        if (int rc = build_batch(nsolves, problems, block, o.width, "fmm_solve_batched", probs)) return rc;
+        RunOut out{};
+        int rc = dispatch(dtype, block, o, probs, (hipStream_t)hip_stream, out);
+        if (per_solve_stats && (rc == 0 || rc == FMM_ENOCONV)) {
+            const int W = o.waves_per_block <= 0 ? 1 : o.waves_per_block;
+            for (int32_t q = 0; q < nsolves; ++q) {
+                const int64_t rq = nsolves > 1 ? (int64_t)out.lastr[q] + 1 : out.ctl.restarts;
+                const int64_t pq = nsolves > 1 ? (int64_t)out.ppops[q] : (int64_t)out.ctl.pops;
+                fill_stats(&per_solve_stats[q], out, block, W, rq, pq);
+                per_solve_stats[q].final_bound =
+                    std::min((double)rq * probs[q].d.stride, probs[q].d.width);
+            }
+        }
+        return rc;
+    } catch (const std::exception &e) {
+        return fail(FMM_EHIP, std::string("fmm_solve_batched: ") + e.what());
+    } catch (...) {
+        return fail(FMM_EHIP, "fmm_solve_batched: unknown exception");
+    }
+}
+
+int fmm_autotune(int32_t nsamples, const fmm_problem *samples, int32_t dtype, const char *cache_path,
+                 void *hip_stream, fmm_tuning *out)
+{
+    try {
+        if (nsamples <= 0 || !samples || !out) return fail(FMM_EINVAL, "fmm_autotune: bad arguments");
+        if (dtype != FMM_F32 && dtype != FMM_F64) return fail(FMM_EINVAL, "fmm_autotune: bad dtype");
+        Device dev;
+        if (int rc = device_info(dev)) return rc;
+        const std::string key = tune_key(dev.name, dtype, nsamples, samples);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            return 0;
+        }
+        fmm_tuning best{0, 0, INFINITY};
+        if (tune_file_lookup(cache_path, key, best)) {
+            g_tune_cache[key] = best;
+            *out = best;
+            return 0;
+        }
+        const int blocks[2] = {8, 16};
+        const int waves[3] = {1, 2, 4};
+        for (int B : blocks) {
+            bool divides = true;
+            for (int32_t q = 0; q < nsamples; ++q)
+                if (samples[q].nx % B || samples[q].ny % B || samples[q].nz % B) divides = false;
+            if (!divides) continue;
+            for (int W : waves) {
+                fmm_options o;
+                fmm_options_default(&o);
+                o.waves_per_block = W;
+                std::vector<Prob> probs;
+                if (int rc = build_batch(nsamples, samples, B, o.width, "fmm_autotune", probs)) return rc;
+                RunOut r1{}, r2{};
+                if (int rc = dispatch(dtype, B, o, probs, (hipStream_t)hip_stream, r1)) return rc;
+                if (int rc = dispatch(dtype, B, o, probs, (hipStream_t)hip_stream, r2)) return rc;
+                if (r2.ms < best.ms) best = fmm_tuning{B, W, (double)r2.ms};
+            }
+        }
+        if (best.block == 0) return fail(FMM_ENOTSUP, "fmm_autotune: no block size divides every sample");
+        g_tune_cache[key] = best;
+        tune_file_store(cache_path, key, best);
+        *out = best;
+        return 0;
+    } catch (const std::exception &e) {
+        return fail(FMM_EHIP, std::string("fmm_autotune: ") + e.what());
+    }
+}
+
+int fmm_selftest_wave_min(const uint32_t *in_dev, uint32_t *out_dev, int32_t nwaves, void *hip_stream)
+{
+    if (!in_dev || !out_dev || nwaves <= 0) return fail(FMM_EINVAL, "fmm_selftest_wave_min: bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    k_wave_min<<<nwaves, 64, 0, st>>>(in_dev, out_dev, nwaves);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+const char *fmm_strerror(int code)
+{
+    switch (code) {
+    case FMM_OK: return "ok";
+    case FMM_EINVAL: return "invalid argument";
+    case FMM_ENOMEM: return "out of memory";
+    case FMM_EHIP: return "HIP runtime error";
+    case FMM_ENOCONV: return "no convergence (restart cap or device watchdog)";
+    case FMM_ENOTSUP: return "not supported";
+    default: return "unknown error code";
+    }
+}
+
+const char *fmm_last_error_detail(void) { return g_detail.c_str(); }
+
+const char *fmm_version(void) { return "fmm-mi355x 0.1 (gfx950)"; }
+
+} // extern "C"

@@ -1,0 +1,719 @@
+// fmm_kernels.hpp -- the phases of one restart of the block-based restarted
+// narrow-band FMM (Alg. 6) as device functions, and the kernels built from
+// them: block set-up (Alg. 1), the persistent restart loop, the per-phase
+// kernels of the host-driven loop, and the copy of the result back to the
+// caller's linear layout.
+#pragma once
+#include "fmm_device.hpp"
+
+namespace fmmdev {
+
+// Row of the per-restart trace; same layout as fmm_trace_row in fmm.h.
+struct TraceRow {
+    float feat[12];
+    double bound;
+    double stride_used;
+    int64_t pops;
+    int64_t t_start;
+    int64_t t_end;
+    int32_t active;
+    int32_t next_active;
+};
+
+constexpr double kLogMinMult = -1.3862943611198906;  // ln(1/4)
+constexpr double kLogSpanMult = 3.4657359027997265;  // ln(8) - ln(1/4)
+constexpr double kFixScale = 1048576.0;              // 2^20, fixed point of speed sums
+
+__device__ __forceinline__ int64_t wall_ticks() { return (int64_t)wall_clock64(); }
+
+__device__ __forceinline__ void raise_error(Ctl *ctl, int code)
+{
+    int expected = 0;
+    __hip_atomic_compare_exchange_strong(&ctl->abort, &expected, code, __ATOMIC_RELAXED,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int read_abort(Ctl *ctl)
+{
+    return __hip_atomic_load(&ctl->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// bound_r = min(r * stride, width) evaluated in double (fixed stride, Alg. 6).
+__device__ __forceinline__ double fixed_bound(int64_t r, double stride, double width)
+{
+    double b = (double)r * stride;
+    return b > width ? width : b;
+}
+
+// Grid-wide barrier for the persistent kernel.  Every work-group's first
+// thread arrives with an agent-scope release and waits for the generation to
+// move with an acquire, so everything written before the barrier by any
+// work-group is visible after it.  The wait is bounded: on timeout, or when
+// another work-group has raised an error, it gives up and the caller leaves
+// the restart loop.
+__device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
+{
+    // every wave publishes its own stores before the work-group arrives
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == G - 1) {
+            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const int64_t t0 = wall_ticks();
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+                   gen) {
+                __builtin_amdgcn_s_sleep(1);
+                if (read_abort(ctl)) break;
+                if (wall_ticks() - t0 > timeout_ticks) {
+                    raise_error(ctl, kErrTimeout);
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- Alg. 4 on one block
+// March_Narrow_Band(ib): load the block's tile, band and tags into LDS, accept
+// band points in increasing (psi, index) order while psi <= bound, relaxing the
+// interior neighbours of each accepted point (Alg. 2 with Alg. 3), then store
+// the tile back, record the new band minimum and raise the exchange flag of
+// every neighbour whose ghost layer meets the updated boundary points.
+template <typename R, int B, int W>
+__device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
+                            char *smem, unsigned long long &pops_acc)
+{
+    using L = Lds<R, B, W>;
+    constexpr int P = Geo<B>::P, T = Geo<B>::T, B3 = Geo<B>::B3, NT = 64 * W;
+    R *s_psi = reinterpret_cast<R *>(smem + L::psi_off);
+    uint16_t *s_band = reinterpret_cast<uint16_t *>(smem + L::band_off);
+    uint8_t *s_tag = reinterpret_cast<uint8_t *>(smem + L::tag_off);
+    char *scr = smem + L::scr_off;
+    int *s_bc = reinterpret_cast<int *>(scr + 64);
+    const int tid = threadIdx.x;
+    const R inf = (R)INFINITY;
+
+    R *g_psi = kp.psi_t + ib * (int64_t)T;
+    uint8_t *g_tag = kp.tag_t + ib * (int64_t)T;
+    uint16_t *g_band = kp.band_t + ib * (int64_t)T;
+    const R *g_rhs = kp.rhs_t + ib * (int64_t)B3;
+
+    // tile -> LDS (16-byte vectors for psi, 4-byte words for tags)
+    if constexpr (sizeof(R) == 4) {
+        const float4 *src = reinterpret_cast<const float4 *>(g_psi);
+        float4 *dst = reinterpret_cast<float4 *>(s_psi);
+        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
+    } else {
+        const double2 *src = reinterpret_cast<const double2 *>(g_psi);
+        double2 *dst = reinterpret_cast<double2 *>(s_psi);
+        for (int i = tid; i < T / 2; i += NT) dst[i] = src[i];
+    }
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(g_tag);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(s_tag);
+        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
+    }
+    int n = kp.band_n[ib];
+    for (int s = tid; s < n; s += NT) s_band[s] = g_band[s];
+    __syncthreads();
+
+    uint32_t dirty = 0;
+    bool active = true;
+    R exit_min = inf;
+    long long npops = 0;
+    for (;;) {
+        if (n == 0) {  // empty heap: deactivate
+            active = false;
+            exit_min = inf;
+            break;
+        }
+        // Locate_Min
+        R bv = inf;
+        int bi = 0xffff, bs = 0;
+        for (int s = tid; s < n; s += NT) {
+            const int id = s_band[s];
+            const R v = s_psi[id];
+            if (v < bv || (v == bv && id < bi)) {
+                bv = v;
+                bi = id;
+                bs = s;
+            }
+        }
+        const MinPick<R> mp = group_argmin<R, W>(bv, bi, bs, scr);
+        if ((double)mp.v > bound) {  // beyond the restart bound: stop (deactivate past width)
+            if ((double)mp.v > pd.width) active = false;
+            exit_min = mp.v;
+            break;
+        }
+        const int p = mp.idx;
+        if (++npops > kp.pop_cap) {
+            raise_error(kp.ctl, kErrPopCap);
+            exit_min = mp.v;
+            break;
+        }
+        // tag KNOWN_NEW unless KNOWN_FIX, then Remove_Min (swap the last entry in)
+        if (tid == 0) {
+            const uint8_t tp = s_tag[p];
+            s_tag[p] = ((tp & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
+            s_band[mp.slot] = s_band[n - 1];
+        }
+        n -= 1;
+        // Update_Neighbors(p): one lane per face neighbour, interior points only
+        if (tid < 64) {
+            const int lane = tid;
+            bool ins = false;
+            int q = 0;
+            uint32_t fb = 0;
+            if (lane < 6) {
+                const int pi = p % P, pj = (p / P) % P, pk = p / (P * P);
+                const int qi = pi + (lane == 1) - (lane == 0);
+                const int qj = pj + (lane == 3) - (lane == 2);
+                const int qk = pk + (lane == 5) - (lane == 4);
+                if (qi >= 1 && qi <= B && qj >= 1 && qj <= B && qk >= 1 && qk <= B) {
+                    q = qi + P * (qj + P * qk);
+                    const uint8_t tq = s_tag[q];
+                    const R psq = s_psi[q];
+                    if ((tq & kStatus) != kKnownFix && psq > mp.v) {
+                        const R rhs = g_rhs[(qi - 1) + B * ((qj - 1) + B * (qk - 1))];
+                        R c[3];
+#pragma unroll
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+                            const R lo = s_psi[q - off], hi = s_psi[q + off];
+                            const bool klo = is_known(s_tag[q - off]) || (q - off == p);
+                            const bool khi = is_known(s_tag[q + off]) || (q + off == p);
+                            c[ax] = axis_candidate<R>(psq, lo, klo, hi, khi);
+                        }
+                        const R t = quad_root<R>(c[0], c[1], c[2], rhs);
+                        if (t < psq) {
+                            s_psi[q] = t;
+                            s_tag[q] = kBand | kInBand;
+                            ins = !(tq & kInBand);
+                            fb = (uint32_t)(qi == 1) | ((uint32_t)(qi == B) << 1) |
+                                 ((uint32_t)(qj == 1) << 2) | ((uint32_t)(qj == B) << 3) |
+                                 ((uint32_t)(qk == 1) << 4) | ((uint32_t)(qk == B) << 5);
+                        }
+                    }
+                }
+            }
+            const uint64_t bal = ballot(ins);
+            if (ins) s_band[n + (int)lanes_below(bal)] = (uint16_t)q;
+            n += (int)__popcll(bal);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) dirty |= (uint32_t)__builtin_amdgcn_readlane((int)fb, k);
+            if constexpr (W > 1) {
+                if (lane == 0) s_bc[0] = n;
+            }
+        }
+        __syncthreads();
+        if constexpr (W > 1) n = s_bc[0];
+    }
+
+    // LDS -> tile
+    if constexpr (sizeof(R) == 4) {
+        const float4 *src = reinterpret_cast<const float4 *>(s_psi);
+        float4 *dst = reinterpret_cast<float4 *>(g_psi);
+        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
+    } else {
+        const double2 *src = reinterpret_cast<const double2 *>(s_psi);
+        double2 *dst = reinterpret_cast<double2 *>(g_psi);
+        for (int i = tid; i < T / 2; i += NT) dst[i] = src[i];
+    }
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(s_tag);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(g_tag);
+        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
+    }
+    for (int s = tid; s < n; s += NT) g_band[s] = s_band[s];
+    if (tid == 0) {
+        kp.band_n[ib] = n;
+        kp.A[ib] = active ? 1 : 0;
+        kp.bmin[ib] = exit_min;
+    }
+    // C^nb(ib) <- TRUE for the neighbours whose ghosts meet Upsilon^ib
+    if (tid < 6 && ((dirty >> tid) & 1u)) {
+        const int64_t loc = ib - pd.blk0;
+        int bx = (int)(loc % pd.mx), by = (int)((loc / pd.mx) % pd.my),
+            bz = (int)(loc / ((int64_t)pd.mx * pd.my));
+        const int f = tid;
+        bx += (f == 1) - (f == 0);
+        by += (f == 3) - (f == 2);
+        bz += (f == 5) - (f == 4);
+        if (bx >= 0 && by >= 0 && bz >= 0 && bx < pd.mx && by < pd.my && bz < pd.mz) {
+            const int64_t nb = pd.blk0 + bx + (int64_t)pd.mx * (by + (int64_t)pd.my * bz);
+            atomicOr(&kp.Cm[nb], 1u << (f ^ 1));
+        }
+    }
+    pops_acc += (unsigned long long)npops;
+    if (kp.nprob > 1 && tid == 0) atomicAdd(&kp.prob_pops[kp.blk_prob[ib]], (unsigned long long)npops);
+    __syncthreads();  // LDS is reused by the next block
+}
+
+// ---------------------------------------------------------------- Alg. 5 on one block
+// Integrate_Ghost_Cell_Data(ib) for the faces flagged in cm.  Every ghost point
+// of a flagged face is compared with the point it copies in the neighbour
+// (the whole face, which fires exactly on the points the neighbour updated in
+// this restart: a ghost copy only ever holds an earlier, larger-or-equal value
+// of the monotonically decreasing neighbour value).  A smaller neighbour value
+// is copied with its category and enters (or moves up in) ib's band.  Then C is
+// cleared and the block is activated when its band minimum is within width.
+// Works directly on the tiles in device memory; returns the new activation and
+// band size to every thread.
+template <typename R, int B, int W>
+__device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, const ProbDesc &pd,
+                               char *smem, bool &a_out, int &n_out)
+{
+    using L = Lds<R, B, W>;
+    constexpr int P = Geo<B>::P, T = Geo<B>::T, NT = 64 * W, FB = B * B;
+    const int tid = threadIdx.x;
+    int *s_cnt = reinterpret_cast<int *>(smem + L::scr_off + 64);
+    using U = typename std::conditional<sizeof(R) == 4, uint32_t, unsigned long long>::type;
+    U *s_min = reinterpret_cast<U *>(smem + L::scr_off + 80);
+    if (tid == 0) {
+        s_cnt[0] = 0;
+        const R inf = (R)INFINITY;
+        U ib_bits;
+        __builtin_memcpy(&ib_bits, &inf, sizeof(R));
+        s_min[0] = ib_bits;
+    }
+    __syncthreads();
+    const int64_t loc = ib - pd.blk0;
+    const int bx = (int)(loc % pd.mx), by = (int)((loc / pd.mx) % pd.my),
+              bz = (int)(loc / ((int64_t)pd.mx * pd.my));
+    R *g_psi = kp.psi_t + ib * (int64_t)T;
+    uint8_t *g_tag = kp.tag_t + ib * (int64_t)T;
+    uint16_t *g_band = kp.band_t + ib * (int64_t)T;
+    const int n0 = kp.band_n[ib];
+    U my_min = ~(U)0;
+    for (int e = tid; e < 6 * FB; e += NT) {
+        const int f = e / FB;
+        if (!((cm >> f) & 1u)) continue;
+        const int a = e % FB % B + 1, b = e % FB / B + 1;
+        const int axis = f >> 1, side = f & 1;
+        const int nbx = bx + (f == 1) - (f == 0), nby = by + (f == 3) - (f == 2),
+                  nbz = bz + (f == 5) - (f == 4);
+        const int64_t nb = pd.blk0 + nbx + (int64_t)pd.mx * (nby + (int64_t)pd.my * nbz);
+        const int gl = side ? B + 1 : 0;  // ghost layer of ib on face f
+        const int nl = side ? 1 : B;      // boundary layer of nb facing ib
+        int gt, st;
+        if (axis == 0) {
+            gt = gl + P * (a + P * b);
+            st = nl + P * (a + P * b);
+        } else if (axis == 1) {
+            gt = a + P * (gl + P * b);
+            st = a + P * (nl + P * b);
+        } else {
+            gt = a + P * (b + P * gl);
+            st = a + P * (b + P * nl);
+        }
+        const R vn = kp.psi_t[nb * (int64_t)T + st];
+        const R vi = g_psi[gt];
+        if (vi > vn) {
+            const uint8_t tn = kp.tag_t[nb * (int64_t)T + st];
+            const uint8_t ti = g_tag[gt];
+            g_psi[gt] = vn;
+            g_tag[gt] = (uint8_t)((tn & kStatus) | kInBand);
+            if (!(ti & kInBand)) {
+                const int pos = atomicAdd(s_cnt, 1);
+                g_band[n0 + pos] = (uint16_t)gt;
+            }
+            U vb;
+            __builtin_memcpy(&vb, &vn, sizeof(R));
+            if (vb < my_min) my_min = vb;
+        }
+    }
+    if (my_min != ~(U)0) atomicMin(s_min, my_min);
+    __syncthreads();
+    int *s_res = reinterpret_cast<int *>(smem + L::scr_off + 72);
+    if (tid == 0) {
+        const int nn = n0 + s_cnt[0];
+        R cmin;
+        U mb = s_min[0];
+        __builtin_memcpy(&cmin, &mb, sizeof(R));
+        R bm = kp.bmin[ib];
+        if (cmin < bm) bm = cmin;
+        kp.bmin[ib] = bm;
+        kp.band_n[ib] = nn;
+        kp.Cm[ib] = 0u;
+        bool a = kp.A[ib] != 0;
+        if (nn > 0 && (double)bm <= pd.width) a = true;
+        kp.A[ib] = a ? 1 : 0;
+        s_res[0] = nn;
+        s_res[1] = a ? 1 : 0;
+    }
+    __syncthreads();
+    n_out = s_res[0];
+    a_out = s_res[1] != 0;
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------- phase drivers
+// Marching step of restart r: blocks of the march list list[r & 1] are taken
+// from a work queue.  A block whose exact band minimum is above its bound is
+// not loaded: Alg. 4 would stop at once without changing anything (only the
+// width test can flip its activation).
+template <typename R, int B, int W>
+__device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem)
+{
+    using L = Lds<R, B, W>;
+    const int c = (int)(r & 1);
+    const int tid = threadIdx.x;
+    Ctl *ctl = kp.ctl;
+    const int32_t *cur = c ? kp.list1 : kp.list0;
+    const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int *s_item = reinterpret_cast<int *>(smem + L::scr_off + 96);
+    unsigned long long pops = 0, mcalls = 0, loads = 0;
+    for (;;) {
+        if (tid == 0) s_item[0] = atomicAdd(&ctl->q_head[c], 1);
+        __syncthreads();
+        const int item = s_item[0];
+        __syncthreads();
+        if (item >= ncur) break;
+        const int64_t ib = cur[item];
+        const ProbDesc &pd = kp.prob[kp.blk_prob[ib]];
+        const double bound = kp.stride_mode ? lbound : fixed_bound(r, pd.stride, pd.width);
+        ++mcalls;
+        const R bm = kp.bmin[ib];
+        if ((double)bm > bound) {
+            if ((double)bm > pd.width && tid == 0) kp.A[ib] = 0;
+            continue;
+        }
+        ++loads;
+        march_block<R, B, W>(kp, ib, pd, bound, smem, pops);
+    }
+    if (tid == 0 && mcalls) {
+        atomicAdd(&ctl->pops, pops);
+        atomicAdd(&ctl->rpops[c], pops);
+        atomicAdd(&ctl->march_calls, mcalls);
+        atomicAdd(&ctl->tile_loads, loads);
+    }
+}
+
+// Exchanging step of restart r, fused with the compaction of the next march
+// list.  Work-group w owns blocks w, w + G, w + 2G, ...; it scans their C flags
+// 64 at a time (ballot), runs Alg. 5 on every flagged one, and appends its
+// blocks whose activation is set to list[(r + 1) & 1] (ballot, in-wave prefix
+// count, one atomic per wave).  The activation of an owned block is final once
+// its own exchange is done, so no extra barrier is needed before compaction.
+template <typename R, int B, int W>
+__device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int G, int w)
+{
+    const int c = (int)(r & 1);
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    Ctl *ctl = kp.ctl;
+    int32_t *next = c ? kp.list0 : kp.list1;
+    unsigned long long xcalls = 0;
+    for (int64_t base = 0; (int64_t)w + (int64_t)G * base < kp.nblk; base += 64) {
+        const int64_t ib = (int64_t)w + (int64_t)G * (base + lane);
+        const bool valid = ib < kp.nblk;
+        const uint32_t cm = valid ? kp.Cm[ib] : 0u;
+        bool a = valid ? (kp.A[ib] != 0) : false;
+        int nb = valid ? kp.band_n[ib] : 0;
+        uint64_t em = ballot(cm != 0u);
+        while (em) {
+            const int l = __ffsll((long long)em) - 1;
+            em &= em - 1;
+            const int64_t ibl = (int64_t)w + (int64_t)G * (base + l);
+            const uint32_t cml = (uint32_t)__builtin_amdgcn_readlane((int)cm, l);
+            const ProbDesc &pd = kp.prob[kp.blk_prob[ibl]];
+            bool an;
+            int nn;
+            exchange_block<R, B, W>(kp, ibl, cml, pd, smem, an, nn);
+            ++xcalls;
+            if (lane == l) {
+                a = an;
+                nb = nn;
+            }
+        }
+        if (wid == 0) {
+            const uint64_t am = ballot(a);
+            if (am) {
+                int pos0 = 0;
+                if (lane == 0) pos0 = atomicAdd(&ctl->n_list[c ^ 1], (int)__popcll(am));
+                pos0 = __builtin_amdgcn_readfirstlane(pos0);
+                if (a) next[pos0 + (int)lanes_below(am)] = (int32_t)ib;
+                if (kp.want_features) {
+                    int bin = 0;
+                    if (nb >= 1) bin = 1;
+                    if (nb >= 4) bin = 2;
+                    if (nb >= 16) bin = 3;
+                    if (nb >= 64) bin = 4;
+                    if (nb >= 256) bin = 5;
+                    if (nb >= 1024) bin = 6;
+                    if (nb >= 4096) bin = 7;
+                    for (int k = 0; k < 8; ++k) {
+                        const int cnt = (int)__popcll(ballot(a && bin == k));
+                        if (lane == 0 && cnt) atomicAdd(&ctl->feat[c ^ 1][k], (unsigned long long)cnt);
+                    }
+                    unsigned long long fx =
+                        a ? (unsigned long long)((double)kp.fmean[ib] * kFixScale + 0.5) : 0ull;
+                    for (int o = 32; o >= 1; o >>= 1) fx += __shfl_xor(fx, o);
+                    if (lane == 0) atomicAdd(&ctl->feat[c ^ 1][8], fx);
+                }
+                if (kp.nprob > 1 && a) atomicMax(&kp.prob_lastr[kp.blk_prob[ib]], (int)r);
+            }
+        }
+    }
+    if (tid == 0 && xcalls) atomicAdd(&ctl->exchange_calls, xcalls);
+}
+
+// ---------------------------------------------------------------- stride network
+// m = exp(ln(1/4) + sigmoid(z) ln 32) for the standardised features, FP32,
+// evaluated identically by every work-group.
+__device__ float mlp_multiplier(const float *blob, const float *raw)
+{
+    const float *W1 = blob, *b1 = W1 + 32 * 12, *W2 = b1 + 32, *b2 = W2 + 32 * 32, *W3 = b2 + 32,
+                *b3 = W3 + 32, *mu = b3 + 1, *sd = mu + 12;
+    float x[12], h1[32];
+    for (int i = 0; i < 12; ++i) x[i] = (raw[i] - mu[i]) / sd[i];
+    for (int o = 0; o < 32; ++o) {
+        float s = b1[o];
+        for (int i = 0; i < 12; ++i) s += W1[o * 12 + i] * x[i];
+        h1[o] = s > 0.f ? s : 0.f;
+    }
+    float z = b3[0];
+    for (int o = 0; o < 32; ++o) {
+        float s = b2[o];
+        for (int i = 0; i < 32; ++i) s += W2[o * 32 + i] * h1[i];
+        z += W3[o] * (s > 0.f ? s : 0.f);
+    }
+    const float sig = 1.0f / (1.0f + expf(-z));
+    const float m = expf((float)kLogMinMult + sig * (float)kLogSpanMult);
+    return m;
+}
+
+// Raw features at the end of restart r (see fmm.h); n_next > 0.
+__device__ void restart_features(const Ctl *ctl, int cn, int n_next, int64_t nblk, double bound,
+                                 int64_t r, const ProbDesc &pd, float *f)
+{
+    const double inv = 1.0 / (double)n_next;
+    f[0] = (float)(bound / ((double)pd.nmax * pd.h));
+    f[1] = (float)((double)n_next / (double)nblk);
+    for (int k = 0; k < 8; ++k) f[2 + k] = (float)((double)ctl->feat[cn][k] * inv);
+    f[10] = (float)((double)r / (double)pd.nmax);
+    f[11] = (float)((double)ctl->feat[cn][8] / kFixScale * inv);
+}
+
+// ---------------------------------------------------------------- persistent restart loop
+// The whole main loop of Alg. 6 in one cooperative launch; two grid barriers
+// per restart (after the marching step, after the exchanging step).  The bound
+// lives in registers, identical in every work-group.
+template <typename R, int B, int W>
+__global__ void __launch_bounds__(64 * W) k_persistent(KParams<R> kp)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int G = (int)gridDim.x, w = (int)blockIdx.x, tid = threadIdx.x;
+    Ctl *ctl = kp.ctl;
+    if (read_abort(ctl)) return;
+    const ProbDesc &p0 = kp.prob[0];
+    double prev_bound = 0.0, lstride = p0.stride, lbound = 0.0;
+    for (int64_t r = 1;; ++r) {
+        const int c = (int)(r & 1);
+        if (kp.stride_mode) {
+            lbound = prev_bound + lstride;
+            if (lbound > p0.width) lbound = p0.width;
+        }
+        int64_t t0 = 0;
+        if (w == 0 && tid == 0) {
+            ctl->n_list[c ^ 1] = 0;
+            ctl->q_head[c ^ 1] = 0;
+            ctl->rpops[c ^ 1] = 0;
+            for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
+            t0 = wall_ticks();
+        }
+        march_phase<R, B, W>(kp, r, lbound, smem);
+        grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
+        if (read_abort(ctl)) break;
+        exchange_phase<R, B, W>(kp, r, smem, G, w);
+        grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
+        if (read_abort(ctl)) break;
+        const int nnext = __hip_atomic_load(&ctl->n_list[c ^ 1], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+        const double bound_r = kp.stride_mode ? lbound : fixed_bound(r, p0.stride, p0.width);
+        float feat[12];
+        if (kp.want_features && nnext > 0)
+            restart_features(ctl, c ^ 1, nnext, kp.nblk, bound_r, r, p0, feat);
+        if (w == 0 && tid == 0 && kp.trace && r <= kp.trace_cap) {
+            TraceRow *row = reinterpret_cast<TraceRow *>(kp.trace) + (r - 1);
+            for (int k = 0; k < 12; ++k) row->feat[k] = nnext > 0 ? feat[k] : 0.f;
+            row->bound = bound_r;
+            row->stride_used = bound_r - prev_bound;
+            row->pops = (int64_t)ctl->rpops[c];
+            row->t_start = t0;
+            row->t_end = wall_ticks();
+            row->active = ctl->n_list[c];
+            row->next_active = nnext;
+        }
+        if (nnext == 0) {
+            if (w == 0 && tid == 0) {
+                ctl->restarts = r;
+                ctl->final_bound = bound_r;
+            }
+            break;
+        }
+        if (r >= kp.max_restarts) {
+            if (w == 0 && tid == 0) {
+                raise_error(ctl, kErrRestarts);
+                ctl->restarts = r;
+                ctl->final_bound = bound_r;
+            }
+            break;
+        }
+        if (kp.stride_mode) {
+            float m = 1.0f;
+            if (kp.mlp) {
+                m = mlp_multiplier(kp.mlp, feat);
+                if (!(m >= 0.25f && m <= 8.0f)) m = 1.0f;  // not finite or out of range
+            }
+            prev_bound = lbound;
+            lstride = (double)m * p0.stride;
+        } else {
+            prev_bound = bound_r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host-driven loop
+template <typename R>
+__global__ void k_restart_prologue(KParams<R> kp, int64_t r)
+{
+    const int c = (int)(r & 1);
+    Ctl *ctl = kp.ctl;
+    ctl->n_list[c ^ 1] = 0;
+    ctl->q_head[c ^ 1] = 0;
+    ctl->rpops[c ^ 1] = 0;
+    for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
+}
+
+template <typename R, int B, int W>
+__global__ void __launch_bounds__(64 * W) k_march(KParams<R> kp, int64_t r)
+{
+    extern __shared__ __align__(16) char smem[];
+    if (read_abort(kp.ctl)) return;
+    march_phase<R, B, W>(kp, r, 0.0, smem);
+}
+
+template <typename R, int B, int W>
+__global__ void __launch_bounds__(64 * W) k_exchange(KParams<R> kp, int64_t r)
+{
+    extern __shared__ __align__(16) char smem[];
+    if (read_abort(kp.ctl)) return;
+    exchange_phase<R, B, W>(kp, r, smem, (int)gridDim.x, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------- Alg. 1 and layout
+// Per block: psi <- +inf and G <- FAR on the padded tile, empty band, A <- F,
+// C <- F; h^2/F^2 of the interior from the caller's linear F; mean speed.
+template <typename R, int B>
+__global__ void __launch_bounds__(256) k_init(KParams<R> kp)
+{
+    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3;
+    __shared__ float s_sum[256];
+    const int tid = threadIdx.x;
+    for (int64_t ib = blockIdx.x; ib < kp.nblk; ib += gridDim.x) {
+        const ProbDesc &pd = kp.prob[kp.blk_prob[ib]];
+        const int64_t loc = ib - pd.blk0;
+        const int64_t bx = loc % pd.mx, by = (loc / pd.mx) % pd.my, bz = loc / ((int64_t)pd.mx * pd.my);
+        R *gp = kp.psi_t + ib * (int64_t)T;
+        uint8_t *gt = kp.tag_t + ib * (int64_t)T;
+        for (int t = tid; t < T; t += 256) {
+            gp[t] = (R)INFINITY;
+            gt[t] = kFar;
+        }
+        R *gr = kp.rhs_t + ib * (int64_t)B3;
+        const R *F = reinterpret_cast<const R *>(pd.F);
+        const R hh = (R)pd.h;
+        float fsum = 0.f;
+        bool bad = false;
+        for (int e = tid; e < B3; e += 256) {
+            const int li = e % B, lj = (e / B) % B, lk = e / (B * B);
+            const int64_t g = (bx * B + li) + (int64_t)pd.nx * ((by * B + lj) + (int64_t)pd.ny * (bz * B + lk));
+            const R f = F[g];
+            if (!(f >= (R)0) || !(f < (R)INFINITY)) bad = true;
+            gr[e] = (hh * hh) / (f * f);
+            fsum += (float)f;
+        }
+        if (bad) raise_error(kp.ctl, kErrBadSpeed);
+        s_sum[tid] = fsum;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s) s_sum[tid] += s_sum[tid + s];
+            __syncthreads();
+        }
+        if (tid == 0) {
+            kp.fmean[ib] = s_sum[0] / (float)B3;
+            kp.band_n[ib] = 0;
+            kp.A[ib] = 0;
+            kp.Cm[ib] = 0u;
+            kp.bmin[ib] = (R)INFINITY;
+        }
+        __syncthreads();
+    }
+}
+
+// Points of Gamma: psi0, KNOWN_FIX, into the band, activate the block (Alg. 1).
+// One entry per (block, tile point), duplicates already merged on the host.
+struct SrcEntry {
+    int64_t ib;
+    int32_t t;
+    int32_t pad;
+    double v;
+};
+
+template <typename R>
+__global__ void k_sources(KParams<R> kp, const SrcEntry *e, int32_t n, int T)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t ib = e[k].ib;
+    const int t = e[k].t;
+    const R v = (R)e[k].v;
+    kp.psi_t[ib * (int64_t)T + t] = v;
+    kp.tag_t[ib * (int64_t)T + t] = kKnownFix | kInBand;
+    const int pos = atomicAdd(&kp.band_n[ib], 1);
+    kp.band_t[ib * (int64_t)T + pos] = (uint16_t)t;
+    kp.A[ib] = 1;
+    using U = typename std::conditional<sizeof(R) == 4, unsigned int, unsigned long long>::type;
+    U vb;
+    __builtin_memcpy(&vb, &v, sizeof(R));
+    atomicMin(reinterpret_cast<U *>(&kp.bmin[ib]), vb);
+}
+
+// Interior of every block -> caller's linear psi.
+template <typename R, int B>
+__global__ void __launch_bounds__(256) k_unlayout(KParams<R> kp)
+{
+    constexpr int P = Geo<B>::P, T = Geo<B>::T, B3 = Geo<B>::B3;
+    const int tid = threadIdx.x;
+    for (int64_t ib = blockIdx.x; ib < kp.nblk; ib += gridDim.x) {
+        const ProbDesc &pd = kp.prob[kp.blk_prob[ib]];
+        const int64_t loc = ib - pd.blk0;
+        const int64_t bx = loc % pd.mx, by = (loc / pd.mx) % pd.my, bz = loc / ((int64_t)pd.mx * pd.my);
+        const R *gp = kp.psi_t + ib * (int64_t)T;
+        R *out = reinterpret_cast<R *>(pd.psi);
+        for (int e = tid; e < B3; e += 256) {
+            const int li = e % B, lj = (e / B) % B, lk = e / (B * B);
+            const int64_t g = (bx * B + li) + (int64_t)pd.nx * ((by * B + lj) + (int64_t)pd.ny * (bz * B + lk));
+            out[g] = gp[(li + 1) + P * ((lj + 1) + P * (lk + 1))];
+        }
+    }
+}
+
+// Diagnostic: per-wave minimum through the same reduction as Locate_Min.
+__global__ void k_wave_min(const uint32_t *in, uint32_t *out, int nwaves)
+{
+    const int wv = blockIdx.x;
+    if (wv >= nwaves) return;
+    const uint32_t m = wave_min_u32(in[(int64_t)wv * 64 + threadIdx.x]);
+    if (threadIdx.x == 0) out[wv] = m;
+}
+
+} // namespace fmmdev

@@ -1,0 +1,319 @@
+"""Python binding of the HIP library (include/fmm.h), argument marshalling only.
+
+Every step of a solve runs in the library's HIP kernels; this module only
+passes device pointers (torch CUDA tensors) and the current HIP stream through
+ctypes.  There is no fallback: if ``libfmm_hip.so`` is missing or no GPU is
+present, calls raise.
+
+Arrays are torch tensors of shape (nz, ny, nx), C-contiguous, float32 or
+float64 on the GPU: the linear index of point (i, j, k) is i + nx*(j + ny*k).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm_hip.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_ENOTSUP = 0, -1, -2, -3, -4, -5
+FMM_F32, FMM_F64 = 0, 1
+STRIDE_FIXED, STRIDE_LEARNED = 0, 1
+LAUNCH_PERSISTENT, LAUNCH_HOST = 0, 1
+NFEAT = 12
+MLP_NPARAMS = 1505
+MLP_BLOB_FLOATS = MLP_NPARAMS + 2 * NFEAT
+
+
+class FmmError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (code {code})")
+        self.code = code
+
+
+class Source(C.Structure):
+    _fields_ = [("i", C.c_int64), ("j", C.c_int64), ("k", C.c_int64), ("psi0", C.c_double)]
+
+
+class Options(C.Structure):
+    _fields_ = [("width", C.c_double), ("stride_mode", C.c_int32), ("mlp_weights", C.c_void_p),
+                ("waves_per_block", C.c_int32), ("launch_mode", C.c_int32),
+                ("max_restarts", C.c_int64), ("grid_limit", C.c_int32),
+                ("trace_dev", C.c_void_p), ("trace_cap", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("restarts", C.c_int64), ("pops", C.c_int64), ("march_calls", C.c_int64),
+                ("exchange_calls", C.c_int64), ("tile_loads", C.c_int64),
+                ("final_bound", C.c_double), ("elapsed_ms", C.c_double), ("grid", C.c_int32),
+                ("block", C.c_int32), ("waves_per_block", C.c_int32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64), ("h", C.c_double),
+                ("F_dev", C.c_void_p), ("psi_dev", C.c_void_p), ("src", C.POINTER(Source)),
+                ("nsrc", C.c_int32), ("stride", C.c_double)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("waves_per_block", C.c_int32), ("ms", C.c_double)]
+
+
+class TraceRow(C.Structure):
+    _fields_ = [("feat", C.c_float * NFEAT), ("bound", C.c_double), ("stride_used", C.c_double),
+                ("pops", C.c_int64), ("t_start", C.c_int64), ("t_end", C.c_int64),
+                ("active", C.c_int32), ("next_active", C.c_int32)]
+
+
+TRACE_ROW_BYTES = C.sizeof(TraceRow)
+_lib = None
+
+
+def load():
+    """Load libfmm_hip.so (built in-tree by __graft_entry__.build()); raise if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run __graft_entry__.build() or paper_1811_00009_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    lib.fmm_options_default.argtypes = [C.POINTER(Options)]
+    lib.fmm_options_default.restype = None
+    lib.fmm_solve.argtypes = [i64, i64, i64, dbl, i32, vp, C.POINTER(Source), i32, i32, dbl, vp,
+                              vp, C.POINTER(Options), C.POINTER(Stats)]
+    lib.fmm_solve.restype = C.c_int
+    lib.fmm_solve_batched.argtypes = [i32, C.POINTER(Problem), i32, i32, C.POINTER(Options), vp,
+                                      C.POINTER(Stats)]
+    lib.fmm_solve_batched.restype = C.c_int
+    lib.fmm_autotune.argtypes = [i32, C.POINTER(Problem), i32, C.c_char_p, vp, C.POINTER(Tuning)]
+    lib.fmm_autotune.restype = C.c_int
+    lib.fmm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+    lib.fmm_mlp_forward.restype = C.c_int
+    lib.fmm_mlp_loss_grad.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+    lib.fmm_mlp_loss_grad.restype = C.c_int
+    lib.fmm_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float, C.c_float, C.c_float, i64, vp]
+    lib.fmm_mlp_adam.restype = C.c_int
+    lib.fmm_mlp_train.argtypes = [vp, vp, vp, i64, i64, C.c_float, vp, vp]
+    lib.fmm_mlp_train.restype = C.c_int
+    lib.fmm_selftest_wave_min.argtypes = [vp, vp, i32, vp]
+    lib.fmm_selftest_wave_min.restype = C.c_int
+    lib.fmm_strerror.argtypes = [C.c_int]
+    lib.fmm_strerror.restype = C.c_char_p
+    lib.fmm_last_error_detail.argtypes = []
+    lib.fmm_last_error_detail.restype = C.c_char_p
+    lib.fmm_version.argtypes = []
+    lib.fmm_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != FMM_OK:
+        lib = load()
+        detail = lib.fmm_last_error_detail().decode(errors="replace")
+        raise FmmError(rc, where, f"{lib.fmm_strerror(rc).decode()}: {detail}")
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float32:
+        return FMM_F32
+    if t.dtype == torch.float64:
+        return FMM_F64
+    raise TypeError("F must be float32 or float64")
+
+
+def _check_tensor(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _sources(sources) -> "C.Array":
+    arr = (Source * max(1, len(sources)))()
+    for s, src in enumerate(sources):
+        arr[s].i, arr[s].j, arr[s].k = int(src[0]), int(src[1]), int(src[2])
+        arr[s].psi0 = float(src[3]) if len(src) > 3 else 0.0
+    return arr
+
+
+def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_per_block=1,
+                 launch="persistent", max_restarts=0, grid_limit=0, trace=None) -> Options:
+    o = Options()
+    load().fmm_options_default(C.byref(o))
+    o.width = float(width)
+    o.stride_mode = STRIDE_LEARNED if stride_mode == "learned" else STRIDE_FIXED
+    if mlp_weights is not None:
+        _check_tensor(mlp_weights, "mlp_weights")
+        o.mlp_weights = mlp_weights.data_ptr()
+    o.waves_per_block = int(waves_per_block)
+    o.launch_mode = LAUNCH_HOST if launch == "host" else LAUNCH_PERSISTENT
+    o.max_restarts = int(max_restarts)
+    o.grid_limit = int(grid_limit)
+    if trace is not None:
+        _check_tensor(trace, "trace")
+        o.trace_dev = trace.data_ptr()
+        o.trace_cap = trace.numel() * trace.element_size() // TRACE_ROW_BYTES
+    return o
+
+
+def solve(F, h: float, sources: Sequence, block: int = 16, stride: Optional[float] = None,
+          out=None, with_stats: bool = False, **opts):
+    """psi for speed F (GPU tensor (nz, ny, nx)) and point sources [(i, j, k[, psi0])]."""
+    import torch
+    lib = load()
+    _check_tensor(F, "F")
+    if F.dim() != 3:
+        raise ValueError("F must have shape (nz, ny, nx)")
+    nz, ny, nx = F.shape
+    if out is None:
+        out = torch.empty_like(F)
+    _check_tensor(out, "out")
+    if out.dtype != F.dtype or out.shape != F.shape:
+        raise ValueError("out must match F in shape and dtype")
+    stride = 2.0 * h if stride is None else float(stride)
+    o = make_options(**opts)
+    src = _sources(sources)
+    st = Stats()
+    rc = lib.fmm_solve(nx, ny, nz, float(h), _dtype_code(F), F.data_ptr(), src, len(sources),
+                       int(block), stride, out.data_ptr(), _stream(), C.byref(o), C.byref(st))
+    _check(rc, "fmm_solve")
+    return (out, st.as_dict()) if with_stats else out
+
+
+def solve_batched(problems: Sequence, block: int = 16, with_stats: bool = False, outs=None,
+                  **opts):
+    """problems: [(F, h, sources[, stride])]; one persistent launch for all of them."""
+    import torch
+    lib = load()
+    n = len(problems)
+    arr = (Problem * n)()
+    keep = []
+    if outs is None:
+        outs = [torch.empty_like(p[0]) for p in problems]
+    dtype = None
+    for q, p in enumerate(problems):
+        F, h, sources = p[0], p[1], p[2]
+        stride = float(p[3]) if len(p) > 3 and p[3] is not None else 2.0 * h
+        _check_tensor(F, f"F[{q}]")
+        d = _dtype_code(F)
+        if dtype is None:
+            dtype = d
+        elif d != dtype:
+            raise ValueError("all problems of a batch must share the dtype")
+        nz, ny, nx = F.shape
+        src = _sources(sources)
+        keep.append(src)
+        arr[q].nx, arr[q].ny, arr[q].nz, arr[q].h = nx, ny, nz, float(h)
+        arr[q].F_dev, arr[q].psi_dev = F.data_ptr(), outs[q].data_ptr()
+        arr[q].src = C.cast(src, C.POINTER(Source))
+        arr[q].nsrc = len(sources)
+        arr[q].stride = stride
+    o = make_options(**opts)
+    stats = (Stats * n)()
+    rc = lib.fmm_solve_batched(n, arr, dtype, int(block), C.byref(o), _stream(), stats)
+    _check(rc, "fmm_solve_batched")
+    if with_stats:
+        return outs, [s.as_dict() for s in stats]
+    return outs
+
+
+def autotune(samples: Sequence, cache_path: Optional[str] = None):
+    """Pick (block, waves_per_block) for problems like `samples` [(F, h, sources[, stride])]."""
+    import torch
+    lib = load()
+    n = len(samples)
+    arr = (Problem * n)()
+    keep, outs = [], []
+    dtype = None
+    for q, p in enumerate(samples):
+        F, h, sources = p[0], p[1], p[2]
+        stride = float(p[3]) if len(p) > 3 and p[3] is not None else 2.0 * h
+        dtype = _dtype_code(F)
+        nz, ny, nx = F.shape
+        src = _sources(sources)
+        o = torch.empty_like(F)
+        keep.append(src)
+        outs.append(o)
+        arr[q].nx, arr[q].ny, arr[q].nz, arr[q].h = nx, ny, nz, float(h)
+        arr[q].F_dev, arr[q].psi_dev = F.data_ptr(), o.data_ptr()
+        arr[q].src = C.cast(src, C.POINTER(Source))
+        arr[q].nsrc = len(sources)
+        arr[q].stride = stride
+    t = Tuning()
+    path = cache_path.encode() if cache_path else None
+    rc = lib.fmm_autotune(n, arr, dtype, path, _stream(), C.byref(t))
+    _check(rc, "fmm_autotune")
+    return {"block": t.block, "waves_per_block": t.waves_per_block, "ms": t.ms}
+
+
+# ------------------------------------------------------------------ stride network
+def mlp_forward(params, x):
+    import torch
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(load().fmm_mlp_forward(params.data_ptr(), x.data_ptr(), x.shape[0], y.data_ptr(),
+                                  _stream()), "fmm_mlp_forward")
+    return y
+
+
+def mlp_loss_grad(params, x, t):
+    import torch
+    loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=x.device)
+    _check(load().fmm_mlp_loss_grad(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0],
+                                    loss.data_ptr(), grad.data_ptr(), _stream()),
+           "fmm_mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, t):
+    _check(load().fmm_mlp_adam(params.data_ptr(), grad.data_ptr(), m.data_ptr(), v.data_ptr(),
+                               float(lr), float(beta1), float(beta2), float(eps), int(t),
+                               _stream()), "fmm_mlp_adam")
+
+
+def mlp_train(params, x, t, steps: int, lr: float, loss_hist=None):
+    _check(load().fmm_mlp_train(params.data_ptr(), x.data_ptr(), t.data_ptr(), x.shape[0],
+                                int(steps), float(lr),
+                                loss_hist.data_ptr() if loss_hist is not None else None,
+                                _stream()), "fmm_mlp_train")
+
+
+def selftest_wave_min(x):
+    """x: uint32 values as an int32 GPU tensor of 64*W elements -> W per-wave minima."""
+    import torch
+    nw = x.numel() // 64
+    out = torch.empty(nw, dtype=torch.int32, device=x.device)
+    _check(load().fmm_selftest_wave_min(x.data_ptr(), out.data_ptr(), nw, _stream()),
+           "fmm_selftest_wave_min")
+    return out
+
+
+def trace_rows(trace_tensor, count: int):
+    """Decode the first `count` trace rows of a trace buffer (after a solve)."""
+    import numpy as np
+    raw = trace_tensor.detach().cpu().numpy().tobytes()
+    rows = []
+    for r in range(count):
+        tr = TraceRow.from_buffer_copy(raw[r * TRACE_ROW_BYTES:(r + 1) * TRACE_ROW_BYTES])
+        rows.append({"feat": np.array(tr.feat[:], dtype=np.float32), "bound": tr.bound,
+                     "stride_used": tr.stride_used, "pops": tr.pops, "t_start": tr.t_start,
+                     "t_end": tr.t_end, "active": tr.active, "next_active": tr.next_active})
+    return rows
+
+
+def version() -> str:
+    return load().fmm_version().decode()
