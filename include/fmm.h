@@ -96,6 +96,8 @@ typedef struct {
     int64_t tile_loads;        /* march calls that had work below the bound                 */
     double final_bound;        /* bound of the last restart                                 */
     double elapsed_ms;         /* device time from the first to the last kernel             */
+    double loop_ms;            /* device time of the restart loop alone (the persistent
+                                  kernel, or all per-phase kernels in host mode)            */
     int32_t grid;              /* persistent workgroups used (0 in host mode)               */
     int32_t block;             /* block edge B used                                        */
     int32_t waves_per_block;   /* waves per block used                                     */

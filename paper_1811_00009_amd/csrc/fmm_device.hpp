@@ -62,7 +62,7 @@ struct KParams {
     uint8_t *tag_t;        // [nblk][T] tags
     uint16_t *band_t;      // [nblk][T] band arrays (tile indices)
     int32_t *band_n;       // [nblk] band sizes
-    R *rhs_t;              // [nblk][B^3] h^2 / F^2 of the interior points
+    R *rhs_t;              // [nblk][T] h^2 / F^2 of the interior points (tile layout)
     R *bmin;               // [nblk] exact minimum of the band (+inf when empty)
     uint8_t *A;            // [nblk] marching activation (Sec. 2.5)
     uint32_t *Cm;          // [nblk] exchange flags C, one bit per face (Sec. 2.6)
@@ -86,29 +86,78 @@ struct KParams {
 };
 
 // ---------------------------------------------------------------- tile geometry
+// The band is a plain array of tile indices; Locate_Min reads it in chunks of
+// 512 slots, lane l taking slots [8l, 8l + 8) of a chunk with one 16-byte LDS
+// read, so the 64 lanes touch consecutive 16-byte pieces (no bank conflicts).
+// BAND slots (a multiple of 512) hold every point of the padded tile.  Tags are
+// padded to a multiple of 16 bytes.  For B <= 8 the block's h^2/F^2 values are
+// staged in LDS as well.
 template <int B>
 struct Geo {
     static constexpr int P = B + 2;
     static constexpr int T = P * P * P;
     static constexpr int B3 = B * B * B;
+    static constexpr int BAND = (T + 511) / 512 * 512;
+    static constexpr int TAGB = (T + 15) / 16 * 16;
+    static constexpr bool RHS_LDS = B <= 8;
 };
 
 template <typename R, int B, int W>
 struct Lds {
     static constexpr int T = Geo<B>::T;
     static constexpr size_t psi_off = 0;
-    static constexpr size_t band_off = psi_off + sizeof(R) * T;
-    static constexpr size_t tag_off = band_off + 2 * T;
-    static constexpr size_t scr_off = (tag_off + T + 15) / 16 * 16;
+    static constexpr size_t band_off = (psi_off + sizeof(R) * T + 15) / 16 * 16;
+    static constexpr size_t tag_off = band_off + 2 * Geo<B>::BAND;
+    static constexpr size_t rhs_off = (tag_off + Geo<B>::TAGB + 15) / 16 * 16;
+    static constexpr size_t scr_off = rhs_off + (Geo<B>::RHS_LDS ? sizeof(R) * T : 0);
     static constexpr size_t bytes = scr_off + 16 * 8 + 64;
 };
 
+// Copy NVEC 16-byte vectors global -> LDS (or back), eight per thread in flight
+// before the first wait.
+template <int NT, int NVEC>
+__device__ __forceinline__ void copy_vec16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int tid)
+{
+    constexpr int PER = (NVEC + NT - 1) / NT;
+    constexpr int BATCH = 8;
+#pragma unroll
+    for (int b0 = 0; b0 < PER; b0 += BATCH) {
+        uint4 r[BATCH];
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j) {
+            const int i = tid + (b0 + j) * NT;
+            if (b0 + j < PER) r[j] = src[i < NVEC ? i : NVEC - 1];  // clamped: always in bounds
+        }
+#pragma unroll
+        for (int j = 0; j < BATCH; ++j) {
+            const int i = tid + (b0 + j) * NT;
+            if (b0 + j < PER && i < NVEC) dst[i] = r[j];
+        }
+    }
+}
+
+// Copy the first n entries (rounded up to 8) of a band array.
+template <int NT>
+__device__ __forceinline__ void copy_band(uint16_t *dst, const uint16_t *src, int n, int tid)
+{
+    const int nvec = (n + 7) >> 3;
+    for (int v0 = 0; v0 < nvec; v0 += 4 * NT) {
+        uint4 r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int v = v0 + tid + j * NT;
+            v = v < nvec ? v : nvec - 1;  // clamped: always in bounds
+            r[j] = reinterpret_cast<const uint4 *>(src)[v];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + tid + j * NT;
+            if (v < nvec) reinterpret_cast<uint4 *>(dst)[v] = r[j];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- cross-lane min
-// Minimum of x over the 64 lanes of the wave, returned in every lane.  Within a
-// row of 16 lanes: DPP quad permutations (xor 1, xor 2), then the half-row and
-// row mirrors; across rows: v_permlane16_swap and v_permlane32_swap, which
-// exchange whole rows between the two operands.  Must be called with all 64
-// lanes active.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x)
 {
     x = min(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false));
@@ -158,60 +207,81 @@ struct MinPick {
     int slot;
 };
 
-// Lexicographic (psi, tile index) minimum over all lanes of the work-group.
-// psi >= 0 so IEEE bit patterns order like the values.  Each lane brings its
-// own best candidate (v, idx, slot); lanes without one bring (+inf, 0xffff).
+// Locate_Min over the band: the lexicographic (psi, tile index) minimum.
+// Each lane scans 8 consecutive slots per 16-byte read, keeping its
+// best (value, key) pair branch-free, key = index << 16 | slot.  psi >= 0, so
+// IEEE bit patterns order like the values; the cross-lane step takes the
+// minimum value first (high then low word for FP64), then the minimum key
+// among the lanes holding it.  Returns the same result in every lane.
 template <typename R, int W>
-__device__ __forceinline__ MinPick<R> group_argmin(R v, int idx, int slot, char *scr)
+__device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const R *s_psi, int n,
+                                                  char *scr)
 {
-    const uint32_t vh = KeyBits<R>::hi(v), vl = KeyBits<R>::lo(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const R inf = (R)INFINITY;
+    R bv = inf;
+    uint32_t bk = ~0u;
+    for (int c0 = wid * 512; c0 < n; c0 += 512 * W) {
+        const int base = c0 + lane * 8;
+        const uint4 raw = *reinterpret_cast<const uint4 *>(s_band + base);
+        const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+        uint32_t ids[8];
+        R vs[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t sl = (uint32_t)(base + j);
+            const uint32_t id = (w4[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+            ids[j] = sl < (uint32_t)n ? id : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) vs[j] = s_psi[ids[j]];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const uint32_t sl = (uint32_t)(base + j);
+            const R v = sl < (uint32_t)n ? vs[j] : inf;
+            const uint32_t key = (ids[j] << 16) | sl;
+            const bool better = (v < bv) | ((v == bv) & (key < bk));
+            bv = better ? v : bv;
+            bk = better ? key : bk;
+        }
+    }
+    const uint32_t vh = KeyBits<R>::hi(bv);
     const uint32_t mh = wave_min_u32(vh);
-    uint32_t ml = 0;
     bool tie = (vh == mh);
-    if (sizeof(R) == 8) {
-        ml = wave_min_u32(tie ? vl : 0xffffffffu);
+    uint32_t ml = 0;
+    if constexpr (sizeof(R) == 8) {
+        const uint32_t vl = KeyBits<R>::lo(bv);
+        ml = wave_min_u32(tie ? vl : ~0u);
         tie = tie && (vl == ml);
     }
-    uint64_t tm = ballot(tie);
-    int win;
-    uint32_t widx;
-    if (__popcll(tm) == 1) {
-        win = __ffsll((long long)tm) - 1;
-        widx = (uint32_t)__builtin_amdgcn_readlane(idx, win);
-    } else {
-        widx = wave_min_u32(tie ? (uint32_t)idx : 0xffffffffu);
-        win = __ffsll((long long)ballot(tie && (uint32_t)idx == widx)) - 1;
-    }
-    int wslot = __builtin_amdgcn_readlane(slot, win);
-    MinPick<R> out{KeyBits<R>::from(mh, ml), (int)widx, wslot};
+    uint32_t mk = wave_min_u32(tie ? bk : ~0u);
+    uint32_t h = mh, l = ml;
     if constexpr (W > 1) {
-        // combine the W wave results through LDS
         uint32_t *s = reinterpret_cast<uint32_t *>(scr);
-        const int wid = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0) {
+        if (lane == 0) {
             s[4 * wid + 0] = mh;
             s[4 * wid + 1] = ml;
-            s[4 * wid + 2] = widx;
-            s[4 * wid + 3] = (uint32_t)wslot;
+            s[4 * wid + 2] = mk;
         }
         __syncthreads();
-        uint32_t bh = s[0], bl = s[1], bi = s[2], bs = s[3];
+        h = s[0];
+        l = s[1];
+        mk = s[2];
 #pragma unroll
         for (int k = 1; k < W; ++k) {
-            uint32_t h2 = s[4 * k], l2 = s[4 * k + 1], i2 = s[4 * k + 2];
-            bool less = (h2 < bh) || (h2 == bh && (l2 < bl || (l2 == bl && i2 < bi)));
+            const uint32_t h2 = s[4 * k], l2 = s[4 * k + 1], k2 = s[4 * k + 2];
+            const bool less = (h2 < h) || (h2 == h && (l2 < l || (l2 == l && k2 < mk)));
             if (less) {
-                bh = h2;
-                bl = l2;
-                bi = i2;
-                bs = s[4 * k + 3];
+                h = h2;
+                l = l2;
+                mk = k2;
             }
         }
-        out.v = KeyBits<R>::from(bh, bl);
-        out.idx = (int)bi;
-        out.slot = (int)bs;
     }
-    return out;
+    h = __builtin_amdgcn_readfirstlane(h);
+    l = __builtin_amdgcn_readfirstlane(l);
+    mk = __builtin_amdgcn_readfirstlane(mk);
+    return MinPick<R>{KeyBits<R>::from(h, l), (int)(mk >> 16), (int)(mk & 0xffffu)};
 }
 
 // ---------------------------------------------------------------- Solve_Quadratic (Alg. 3)

@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fmm.h"
+#include "fmm.h"
 #include "fmm_kernels.hpp"
 
 using namespace fmmdev;
@@ -73,7 +73,7 @@ int ensure(DevBuf &b, size_t bytes, const char *what)
 struct Workspace {
     DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, list0, list1, ctl, prob, src,
         plastr, ppops;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, l0 = nullptr, l1 = nullptr;
 };
 
 std::mutex g_mu;
@@ -205,6 +205,7 @@ int map_device_error(int code)
 struct RunOut {
     Ctl ctl;
     float ms;
+    float loop_ms;
     int grid;
     std::vector<int32_t> lastr;
     std::vector<unsigned long long> ppops;
@@ -213,7 +214,7 @@ struct RunOut {
 template <typename R, int B, int W>
 int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, RunOut &out)
 {
-    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3;
+    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3, BAND = Geo<B>::BAND, TAGB = Geo<B>::TAGB;
     using L = Lds<R, B, W>;
     Device dev;
     if (int rc = device_info(dev)) return rc;
@@ -237,10 +238,10 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
 
     int rc = 0;
     if ((rc = ensure(ws.psi, (size_t)nblk * T * sizeof(R), "psi tiles")) ||
-        (rc = ensure(ws.tag, (size_t)nblk * T, "tag tiles")) ||
-        (rc = ensure(ws.band, (size_t)nblk * T * 2, "band arrays")) ||
+        (rc = ensure(ws.tag, (size_t)nblk * TAGB, "tag tiles")) ||
+        (rc = ensure(ws.band, (size_t)nblk * BAND * 2, "band arrays")) ||
         (rc = ensure(ws.bandn, (size_t)nblk * 4, "band sizes")) ||
-        (rc = ensure(ws.rhs, (size_t)nblk * B3 * sizeof(R), "rhs tiles")) ||
+        (rc = ensure(ws.rhs, (size_t)nblk * T * sizeof(R), "rhs tiles")) ||
         (rc = ensure(ws.bmin, (size_t)nblk * sizeof(R), "band minima")) ||
         (rc = ensure(ws.A, (size_t)nblk, "activation flags")) ||
         (rc = ensure(ws.Cm, (size_t)nblk * 4, "exchange flags")) ||
@@ -256,6 +257,8 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     if (!ws.e0) {
         HIPCHK(hipEventCreate(&ws.e0));
         HIPCHK(hipEventCreate(&ws.e1));
+        HIPCHK(hipEventCreate(&ws.l0));
+        HIPCHK(hipEventCreate(&ws.l1));
     }
 
     std::vector<SrcEntry> ents;
@@ -311,12 +314,13 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
         kp.blk_prob, kp.prob, nprob, nblk);
     k_init<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
     if (!ents.empty())
-        k_sources<R><<<(unsigned)((ents.size() + 127) / 128), 128, 0, st>>>(
-            kp, (const SrcEntry *)ws.src.p, (int32_t)ents.size(), T);
+        k_sources<R, B><<<(unsigned)((ents.size() + 127) / 128), 128, 0, st>>>(
+            kp, (const SrcEntry *)ws.src.p, (int32_t)ents.size());
     HIPCHK(hipGetLastError());
 
     int per_cu = 0;
     int grid = 0;
+    HIPCHK(hipEventRecord(ws.l0, st));
     if (o.launch_mode == FMM_LAUNCH_PERSISTENT) {
         auto kern = k_persistent<R, B, W>;
         HIPCHK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -366,6 +370,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
         HIPCHK(hipMemcpyAsync(&dctl->restarts, &rr, sizeof(rr), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(&dctl->final_bound, &fb, sizeof(fb), hipMemcpyHostToDevice, st));
     }
+    HIPCHK(hipEventRecord(ws.l1, st));
     k_unlayout<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(ws.e1, st));
@@ -376,6 +381,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     HIPCHK(hipMemcpyAsync(out.ppops.data(), ws.ppops.p, sizeof(unsigned long long) * nprob, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipEventElapsedTime(&out.ms, ws.e0, ws.e1));
+    HIPCHK(hipEventElapsedTime(&out.loop_ms, ws.l0, ws.l1));
     out.grid = grid;
     return map_device_error(out.ctl.abort);
 }
@@ -434,6 +440,7 @@ void fill_stats(fmm_stats *s, const RunOut &r, int B, int W, int64_t restarts, i
     s->tile_loads = (int64_t)r.ctl.tile_loads;
     s->final_bound = r.ctl.final_bound;
     s->elapsed_ms = r.ms;
+    s->loop_ms = r.loop_ms;
     s->grid = r.grid;
     s->block = B;
     s->waves_per_block = W;

@@ -51,6 +51,11 @@ __device__ __forceinline__ double fixed_bound(int64_t r, double stride, double w
 // work-group is visible after it.  The wait is bounded: on timeout, or when
 // another work-group has raised an error, it gives up and the caller leaves
 // the restart loop.
+//
+// The wait polls with relaxed agent-scope loads (they read the coherent value
+// without touching the caches) and acquires once after the generation moved:
+// an acquire on every poll would invalidate the XCD's L2 under the work-groups
+// that are still working.
 __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
 {
     // every wave publishes its own stores before the work-group arrives
@@ -59,20 +64,24 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
     if (threadIdx.x == 0) {
         const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL,
+        const unsigned prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELEASE,
                                                      __HIP_MEMORY_SCOPE_AGENT);
         if (prev == G - 1) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const int64_t t0 = wall_ticks();
-            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) ==
+            int polls = 0;
+            while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
                    gen) {
-                __builtin_amdgcn_s_sleep(1);
-                if (read_abort(ctl)) break;
-                if (wall_ticks() - t0 > timeout_ticks) {
-                    raise_error(ctl, kErrTimeout);
-                    break;
+                __builtin_amdgcn_s_sleep(2);
+                if ((++polls & 63) == 0) {
+                    if (read_abort(ctl)) break;
+                    if (wall_ticks() - t0 > timeout_ticks) {
+                        raise_error(ctl, kErrTimeout);
+                        break;
+                    }
                 }
             }
         }
@@ -87,44 +96,50 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
 // interior neighbours of each accepted point (Alg. 2 with Alg. 3), then store
 // the tile back, record the new band minimum and raise the exchange flag of
 // every neighbour whose ghost layer meets the updated boundary points.
+//
+// One accepted point costs two LDS round trips for Locate_Min (a 16-byte read
+// of 8 band slots per lane, then the 8 psi values) and two for Update_Neighbors
+// (lanes 0-5 read the neighbour's tag and psi while lane 6 reads the accepted
+// point's tag and lane 7 the band's last slot; then the six stencils), with the
+// h^2/F^2 load of every neighbour issued ahead of both.
 template <typename R, int B, int W>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
                             char *smem, unsigned long long &pops_acc)
 {
     using L = Lds<R, B, W>;
-    constexpr int P = Geo<B>::P, T = Geo<B>::T, B3 = Geo<B>::B3, NT = 64 * W;
+    using Gm = Geo<B>;
+    constexpr int P = Gm::P, T = Gm::T, NT = 64 * W, BAND = Gm::BAND, TAGB = Gm::TAGB;
     R *s_psi = reinterpret_cast<R *>(smem + L::psi_off);
     uint16_t *s_band = reinterpret_cast<uint16_t *>(smem + L::band_off);
     uint8_t *s_tag = reinterpret_cast<uint8_t *>(smem + L::tag_off);
     char *scr = smem + L::scr_off;
     int *s_bc = reinterpret_cast<int *>(scr + 64);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const R inf = (R)INFINITY;
 
     R *g_psi = kp.psi_t + ib * (int64_t)T;
-    uint8_t *g_tag = kp.tag_t + ib * (int64_t)T;
-    uint16_t *g_band = kp.band_t + ib * (int64_t)T;
-    const R *g_rhs = kp.rhs_t + ib * (int64_t)B3;
+    uint8_t *g_tag = kp.tag_t + ib * (int64_t)TAGB;
+    uint16_t *g_band = kp.band_t + ib * (int64_t)BAND;
+    const R *g_rhs = kp.rhs_t + ib * (int64_t)T;
 
-    // tile -> LDS (16-byte vectors for psi, 4-byte words for tags)
-    if constexpr (sizeof(R) == 4) {
-        const float4 *src = reinterpret_cast<const float4 *>(g_psi);
-        float4 *dst = reinterpret_cast<float4 *>(s_psi);
-        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
-    } else {
-        const double2 *src = reinterpret_cast<const double2 *>(g_psi);
-        double2 *dst = reinterpret_cast<double2 *>(s_psi);
-        for (int i = tid; i < T / 2; i += NT) dst[i] = src[i];
-    }
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(g_tag);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(s_tag);
-        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
-    }
     int n = kp.band_n[ib];
-    for (int s = tid; s < n; s += NT) s_band[s] = g_band[s];
+    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(s_psi),
+                                               reinterpret_cast<const uint4 *>(g_psi), tid);
+    copy_vec16<NT, TAGB / 16>(reinterpret_cast<uint4 *>(s_tag), reinterpret_cast<const uint4 *>(g_tag), tid);
+    copy_band<NT>(s_band, g_band, n, tid);
+    const R *rhs_src = g_rhs;
+    if constexpr (Gm::RHS_LDS) {
+        R *s_rhs = reinterpret_cast<R *>(smem + L::rhs_off);
+        copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(s_rhs),
+                                                   reinterpret_cast<const uint4 *>(g_rhs), tid);
+        rhs_src = s_rhs;
+    }
     __syncthreads();
 
+    // per-lane neighbour direction of Update_Neighbors: lanes 0-5 = -x, +x, -y, +y, -z, +z
+    const int dI = (lane == 1) - (lane == 0), dJ = (lane == 3) - (lane == 2),
+              dK = (lane == 5) - (lane == 4);
+    const int dOff = dI + P * (dJ + P * dK);
     uint32_t dirty = 0;
     bool active = true;
     R exit_min = inf;
@@ -135,19 +150,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             exit_min = inf;
             break;
         }
-        // Locate_Min
-        R bv = inf;
-        int bi = 0xffff, bs = 0;
-        for (int s = tid; s < n; s += NT) {
-            const int id = s_band[s];
-            const R v = s_psi[id];
-            if (v < bv || (v == bv && id < bi)) {
-                bv = v;
-                bi = id;
-                bs = s;
-            }
-        }
-        const MinPick<R> mp = group_argmin<R, W>(bv, bi, bs, scr);
+        const MinPick<R> mp = band_argmin<R, W>(s_band, s_psi, n, scr);
         if ((double)mp.v > bound) {  // beyond the restart bound: stop (deactivate past width)
             if ((double)mp.v > pd.width) active = false;
             exit_min = mp.v;
@@ -159,49 +162,43 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             exit_min = mp.v;
             break;
         }
-        // tag KNOWN_NEW unless KNOWN_FIX, then Remove_Min (swap the last entry in)
-        if (tid == 0) {
-            const uint8_t tp = s_tag[p];
-            s_tag[p] = ((tp & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
-            s_band[mp.slot] = s_band[n - 1];
-        }
-        n -= 1;
-        // Update_Neighbors(p): one lane per face neighbour, interior points only
-        if (tid < 64) {
-            const int lane = tid;
+        n -= 1;  // Remove_Min: the last slot moves into the hole (lane 7 below)
+        // Update_Neighbors(p): lanes 0-5 take the six face neighbours (interior only)
+        if (wid == 0) {
+            const uint32_t up = (uint32_t)p;
+            const int pi = (int)(up % P), pj = (int)((up / P) % P), pk = (int)(up / (P * P));
+            const int qi = pi + dI, qj = pj + dJ, qk = pk + dK;
+            const bool inb = lane < 6 && (unsigned)(qi - 1) < (unsigned)B &&
+                             (unsigned)(qj - 1) < (unsigned)B && (unsigned)(qk - 1) < (unsigned)B;
+            const int q = inb ? p + dOff : p;
+            R rhs = (R)0;
+            if (inb) rhs = rhs_src[q];
+            const uint8_t tq = s_tag[q];  // lane 6 reads the accepted point's own tag
+            const R psq = s_psi[q];
+            const uint16_t last = s_band[n];
+            if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
+                s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
+            if (lane == 7) s_band[mp.slot] = last;
             bool ins = false;
-            int q = 0;
             uint32_t fb = 0;
-            if (lane < 6) {
-                const int pi = p % P, pj = (p / P) % P, pk = p / (P * P);
-                const int qi = pi + (lane == 1) - (lane == 0);
-                const int qj = pj + (lane == 3) - (lane == 2);
-                const int qk = pk + (lane == 5) - (lane == 4);
-                if (qi >= 1 && qi <= B && qj >= 1 && qj <= B && qk >= 1 && qk <= B) {
-                    q = qi + P * (qj + P * qk);
-                    const uint8_t tq = s_tag[q];
-                    const R psq = s_psi[q];
-                    if ((tq & kStatus) != kKnownFix && psq > mp.v) {
-                        const R rhs = g_rhs[(qi - 1) + B * ((qj - 1) + B * (qk - 1))];
-                        R c[3];
+            if (inb && (tq & kStatus) != kKnownFix && psq > mp.v) {
+                R c[3];
 #pragma unroll
-                        for (int ax = 0; ax < 3; ++ax) {
-                            const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
-                            const R lo = s_psi[q - off], hi = s_psi[q + off];
-                            const bool klo = is_known(s_tag[q - off]) || (q - off == p);
-                            const bool khi = is_known(s_tag[q + off]) || (q + off == p);
-                            c[ax] = axis_candidate<R>(psq, lo, klo, hi, khi);
-                        }
-                        const R t = quad_root<R>(c[0], c[1], c[2], rhs);
-                        if (t < psq) {
-                            s_psi[q] = t;
-                            s_tag[q] = kBand | kInBand;
-                            ins = !(tq & kInBand);
-                            fb = (uint32_t)(qi == 1) | ((uint32_t)(qi == B) << 1) |
-                                 ((uint32_t)(qj == 1) << 2) | ((uint32_t)(qj == B) << 3) |
-                                 ((uint32_t)(qk == 1) << 4) | ((uint32_t)(qk == B) << 5);
-                        }
-                    }
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+                    const R lo = s_psi[q - off], hi = s_psi[q + off];
+                    const bool klo = is_known(s_tag[q - off]) || (q - off == p);
+                    const bool khi = is_known(s_tag[q + off]) || (q + off == p);
+                    c[ax] = axis_candidate<R>(psq, lo, klo, hi, khi);
+                }
+                const R t = quad_root<R>(c[0], c[1], c[2], rhs);
+                if (t < psq) {
+                    s_psi[q] = t;
+                    s_tag[q] = kBand | kInBand;
+                    ins = !(tq & kInBand);
+                    fb = (uint32_t)(qi == 1) | ((uint32_t)(qi == B) << 1) |
+                         ((uint32_t)(qj == 1) << 2) | ((uint32_t)(qj == B) << 3) |
+                         ((uint32_t)(qk == 1) << 4) | ((uint32_t)(qk == B) << 5);
                 }
             }
             const uint64_t bal = ballot(ins);
@@ -213,26 +210,22 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 if (lane == 0) s_bc[0] = n;
             }
         }
-        __syncthreads();
-        if constexpr (W > 1) n = s_bc[0];
+        if constexpr (W > 1) {
+            __syncthreads();
+            n = s_bc[0];
+        } else {
+            // one wave: its LDS operations complete in program order; keep the
+            // compiler from moving them across iterations
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
     }
 
     // LDS -> tile
-    if constexpr (sizeof(R) == 4) {
-        const float4 *src = reinterpret_cast<const float4 *>(s_psi);
-        float4 *dst = reinterpret_cast<float4 *>(g_psi);
-        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
-    } else {
-        const double2 *src = reinterpret_cast<const double2 *>(s_psi);
-        double2 *dst = reinterpret_cast<double2 *>(g_psi);
-        for (int i = tid; i < T / 2; i += NT) dst[i] = src[i];
-    }
-    {
-        const uint32_t *src = reinterpret_cast<const uint32_t *>(s_tag);
-        uint32_t *dst = reinterpret_cast<uint32_t *>(g_tag);
-        for (int i = tid; i < T / 4; i += NT) dst[i] = src[i];
-    }
-    for (int s = tid; s < n; s += NT) g_band[s] = s_band[s];
+    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(g_psi),
+                                               reinterpret_cast<const uint4 *>(s_psi), tid);
+    copy_vec16<NT, TAGB / 16>(reinterpret_cast<uint4 *>(g_tag), reinterpret_cast<const uint4 *>(s_tag), tid);
+    copy_band<NT>(g_band, s_band, n, tid);
     if (tid == 0) {
         kp.band_n[ib] = n;
         kp.A[ib] = active ? 1 : 0;
@@ -272,7 +265,8 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
                                char *smem, bool &a_out, int &n_out)
 {
     using L = Lds<R, B, W>;
-    constexpr int P = Geo<B>::P, T = Geo<B>::T, NT = 64 * W, FB = B * B;
+    constexpr int P = Geo<B>::P, T = Geo<B>::T, NT = 64 * W, FB = B * B, BAND = Geo<B>::BAND,
+                  TAGB = Geo<B>::TAGB;
     const int tid = threadIdx.x;
     int *s_cnt = reinterpret_cast<int *>(smem + L::scr_off + 64);
     using U = typename std::conditional<sizeof(R) == 4, uint32_t, unsigned long long>::type;
@@ -289,8 +283,8 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
     const int bx = (int)(loc % pd.mx), by = (int)((loc / pd.mx) % pd.my),
               bz = (int)(loc / ((int64_t)pd.mx * pd.my));
     R *g_psi = kp.psi_t + ib * (int64_t)T;
-    uint8_t *g_tag = kp.tag_t + ib * (int64_t)T;
-    uint16_t *g_band = kp.band_t + ib * (int64_t)T;
+    uint8_t *g_tag = kp.tag_t + ib * (int64_t)TAGB;
+    uint16_t *g_band = kp.band_t + ib * (int64_t)BAND;
     const int n0 = kp.band_n[ib];
     U my_min = ~(U)0;
     for (int e = tid; e < 6 * FB; e += NT) {
@@ -317,7 +311,7 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
         const R vn = kp.psi_t[nb * (int64_t)T + st];
         const R vi = g_psi[gt];
         if (vi > vn) {
-            const uint8_t tn = kp.tag_t[nb * (int64_t)T + st];
+            const uint8_t tn = kp.tag_t[nb * (int64_t)TAGB + st];
             const uint8_t ti = g_tag[gt];
             g_psi[gt] = vn;
             g_tag[gt] = (uint8_t)((tn & kStatus) | kInBand);
@@ -378,7 +372,7 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         __syncthreads();
         if (item >= ncur) break;
         const int64_t ib = cur[item];
-        const ProbDesc &pd = kp.prob[kp.blk_prob[ib]];
+        const ProbDesc pd = kp.nprob == 1 ? kp.prob[0] : kp.prob[kp.blk_prob[ib]];
         const double bound = kp.stride_mode ? lbound : fixed_bound(r, pd.stride, pd.width);
         ++mcalls;
         const R bm = kp.bmin[ib];
@@ -423,7 +417,7 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
             em &= em - 1;
             const int64_t ibl = (int64_t)w + (int64_t)G * (base + l);
             const uint32_t cml = (uint32_t)__builtin_amdgcn_readlane((int)cm, l);
-            const ProbDesc &pd = kp.prob[kp.blk_prob[ibl]];
+            const ProbDesc pd = kp.nprob == 1 ? kp.prob[0] : kp.prob[kp.blk_prob[ibl]];
             bool an;
             int nn;
             exchange_block<R, B, W>(kp, ibl, cml, pd, smem, an, nn);
@@ -615,7 +609,7 @@ __global__ void __launch_bounds__(64 * W) k_exchange(KParams<R> kp, int64_t r)
 template <typename R, int B>
 __global__ void __launch_bounds__(256) k_init(KParams<R> kp)
 {
-    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3;
+    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3, TAGB = Geo<B>::TAGB;
     __shared__ float s_sum[256];
     const int tid = threadIdx.x;
     for (int64_t ib = blockIdx.x; ib < kp.nblk; ib += gridDim.x) {
@@ -623,12 +617,10 @@ __global__ void __launch_bounds__(256) k_init(KParams<R> kp)
         const int64_t loc = ib - pd.blk0;
         const int64_t bx = loc % pd.mx, by = (loc / pd.mx) % pd.my, bz = loc / ((int64_t)pd.mx * pd.my);
         R *gp = kp.psi_t + ib * (int64_t)T;
-        uint8_t *gt = kp.tag_t + ib * (int64_t)T;
-        for (int t = tid; t < T; t += 256) {
-            gp[t] = (R)INFINITY;
-            gt[t] = kFar;
-        }
-        R *gr = kp.rhs_t + ib * (int64_t)B3;
+        uint8_t *gt = kp.tag_t + ib * (int64_t)TAGB;
+        for (int t = tid; t < T; t += 256) gp[t] = (R)INFINITY;
+        for (int t = tid; t < TAGB; t += 256) gt[t] = kFar;
+        R *gr = kp.rhs_t + ib * (int64_t)T;
         const R *F = reinterpret_cast<const R *>(pd.F);
         const R hh = (R)pd.h;
         float fsum = 0.f;
@@ -638,7 +630,7 @@ __global__ void __launch_bounds__(256) k_init(KParams<R> kp)
             const int64_t g = (bx * B + li) + (int64_t)pd.nx * ((by * B + lj) + (int64_t)pd.ny * (bz * B + lk));
             const R f = F[g];
             if (!(f >= (R)0) || !(f < (R)INFINITY)) bad = true;
-            gr[e] = (hh * hh) / (f * f);
+            gr[(li + 1) + Geo<B>::P * ((lj + 1) + Geo<B>::P * (lk + 1))] = (hh * hh) / (f * f);
             fsum += (float)f;
         }
         if (bad) raise_error(kp.ctl, kErrBadSpeed);
@@ -668,18 +660,19 @@ struct SrcEntry {
     double v;
 };
 
-template <typename R>
-__global__ void k_sources(KParams<R> kp, const SrcEntry *e, int32_t n, int T)
+template <typename R, int B>
+__global__ void k_sources(KParams<R> kp, const SrcEntry *e, int32_t n)
 {
+    constexpr int T = Geo<B>::T, BAND = Geo<B>::BAND, TAGB = Geo<B>::TAGB;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t ib = e[k].ib;
     const int t = e[k].t;
     const R v = (R)e[k].v;
     kp.psi_t[ib * (int64_t)T + t] = v;
-    kp.tag_t[ib * (int64_t)T + t] = kKnownFix | kInBand;
+    kp.tag_t[ib * (int64_t)TAGB + t] = kKnownFix | kInBand;
     const int pos = atomicAdd(&kp.band_n[ib], 1);
-    kp.band_t[ib * (int64_t)T + pos] = (uint16_t)t;
+    kp.band_t[ib * (int64_t)BAND + pos] = (uint16_t)t;
     kp.A[ib] = 1;
     using U = typename std::conditional<sizeof(R) == 4, unsigned int, unsigned long long>::type;
     U vb;

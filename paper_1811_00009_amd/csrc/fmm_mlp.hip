@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fmm.h"
+#include "fmm.h"
 
 void fmm_internal_set_detail(const std::string &msg);
 

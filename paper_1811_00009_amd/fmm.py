@@ -47,7 +47,8 @@ class Options(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("restarts", C.c_int64), ("pops", C.c_int64), ("march_calls", C.c_int64),
                 ("exchange_calls", C.c_int64), ("tile_loads", C.c_int64),
-                ("final_bound", C.c_double), ("elapsed_ms", C.c_double), ("grid", C.c_int32),
+                ("final_bound", C.c_double), ("elapsed_ms", C.c_double), ("loop_ms", C.c_double),
+                ("grid", C.c_int32),
                 ("block", C.c_int32), ("waves_per_block", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
