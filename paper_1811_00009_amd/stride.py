@@ -1,0 +1,117 @@
+"""Learned restart stride: traces, labels, training driver and weight blobs.
+
+The paper leaves the stride a free parameter and finds about 2h a good fixed
+choice (Sec. 3.5-3.6); smaller strides favour coarse grids with fast-varying
+speed, larger ones favour simple fronts.  Here a 12-32-32-1 network evaluated on
+the device at the end of every restart picks the next stride as m * stride0,
+m in [1/4, 8].  Any bound sequence reaches the same solution (the stride only
+schedules the restarts), so the network trades time, never accuracy.
+
+Data flow (all GPU work through the library's C ABI):
+  1. trace plain solves with fixed multipliers m in MULTIPLIERS: every restart
+     records its raw features, bound and device time;
+  2. label: per field and per bin of the bound fraction, m* = the multiplier
+     with the highest front progress rate (bound advance per device second);
+     every trace row of that bin gets the target ln m*;
+  3. standardise the features (training-set mean and std) and fit the network
+     with the library's forward / backward / Adam kernels (full batch);
+  4. pack the parameters and the standardisation into the device blob that
+     fmm_options.mlp_weights points to.
+"""
+from __future__ import annotations
+
+import math
+from typing import List, Sequence
+
+import numpy as np
+
+NFEAT = 12
+NPARAMS = 1505
+MULTIPLIERS = (0.25, 0.5, 1.0, 2.0, 4.0, 8.0)
+LOG_MIN, LOG_MAX = math.log(0.25), math.log(8.0)
+TICKS_PER_S = 1.0e8  # device wall clock
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """He-initialised parameters, output bias 0 (m = sqrt(1/4 * 8) = 1.41 at start)."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.normal(0, math.sqrt(2.0 / 12), size=(32, 12))
+    W2 = rng.normal(0, math.sqrt(2.0 / 32), size=(32, 32))
+    W3 = rng.normal(0, math.sqrt(1.0 / 32), size=(1, 32))
+    parts = [W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), W3.ravel(), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def pack_blob(params: np.ndarray, mean: np.ndarray, std: np.ndarray) -> np.ndarray:
+    p = np.asarray(params, dtype=np.float32).ravel()
+    assert p.size == NPARAMS
+    return np.concatenate([p, np.asarray(mean, np.float32), np.asarray(std, np.float32)])
+
+
+def trace_solve(fmm, F, h, sources, block=16, stride0=None, multiplier=1.0, rows=20000,
+                blob=None):
+    """One traced solve; returns (psi, stats, trace rows)."""
+    import torch
+    stride0 = 2.0 * h if stride0 is None else stride0
+    trace = torch.zeros(rows * fmm.TRACE_ROW_BYTES, dtype=torch.uint8, device=F.device)
+    kw = {}
+    if blob is not None:
+        kw = dict(stride_mode="learned", mlp_weights=blob)
+        stride = stride0
+    else:
+        stride = multiplier * stride0
+    psi, st = fmm.solve(F, h, sources, block=block, stride=stride, with_stats=True, trace=trace,
+                        **kw)
+    torch.cuda.synchronize()
+    n = min(st["restarts"], rows)
+    return psi, st, fmm.trace_rows(trace, n)
+
+
+def label_traces(traces_by_m: dict, nbins: int = 16):
+    """traces_by_m: {m: rows} for one field.  Returns (X, y): raw features of every
+    row and the target ln m* of its bound-fraction bin."""
+    fmax = max(max(r["feat"][0] for r in rows) for rows in traces_by_m.values() if rows)
+    edges = np.linspace(0.0, fmax * (1 + 1e-9), nbins + 1)
+    rate = {m: np.zeros(nbins) for m in traces_by_m}
+    for m, rows in traces_by_m.items():
+        adv = np.zeros(nbins)
+        tim = np.zeros(nbins)
+        prev = 0.0
+        for r in rows:
+            b = int(np.clip(np.searchsorted(edges, r["feat"][0], side="right") - 1, 0, nbins - 1))
+            adv[b] += r["bound"] - prev
+            tim[b] += max(r["t_end"] - r["t_start"], 1) / TICKS_PER_S
+            prev = r["bound"]
+        rate[m] = np.where(tim > 0, adv / np.maximum(tim, 1e-12), 0.0)
+    ms = sorted(traces_by_m)
+    best = np.array([ms[int(np.argmax([rate[m][b] for m in ms]))] for b in range(nbins)])
+    X, y = [], []
+    for m, rows in traces_by_m.items():
+        for r in rows:
+            if r["next_active"] == 0:
+                continue  # the last restart has no next stride to choose
+            b = int(np.clip(np.searchsorted(edges, r["feat"][0], side="right") - 1, 0, nbins - 1))
+            X.append(r["feat"])
+            y.append(math.log(best[b]))
+    return np.array(X, dtype=np.float32).reshape(-1, NFEAT), np.array(y, dtype=np.float32)
+
+
+def standardise(X: np.ndarray):
+    mean = X.mean(axis=0)
+    std = X.std(axis=0)
+    std = np.where(std > 1e-6, std, 1.0)
+    return mean.astype(np.float32), std.astype(np.float32)
+
+
+def train(fmm, X: np.ndarray, y: np.ndarray, steps: int = 2000, lr: float = 3e-3, seed: int = 0):
+    """Fit on the GPU with the library's kernels.  Returns (blob, params, loss history)."""
+    import torch
+    mean, std = standardise(X)
+    Xs = ((X - mean) / std).astype(np.float32)
+    params = torch.from_numpy(init_params(seed)).cuda()
+    xd = torch.from_numpy(np.ascontiguousarray(Xs)).cuda()
+    yd = torch.from_numpy(np.ascontiguousarray(y)).cuda()
+    hist = torch.zeros(steps, dtype=torch.float32, device="cuda")
+    fmm.mlp_train(params, xd, yd, steps, lr, hist)
+    p = params.cpu().numpy()
+    return pack_blob(p, mean, std), p, hist.cpu().numpy()

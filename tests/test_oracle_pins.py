@@ -364,3 +364,24 @@ def test_adam_step_matches_closed_form_first_step():
     m, v = np.zeros(3), np.zeros(3)
     oracle.adam_step(P, g, m, v, 0.01, 0.9, 0.999, 1e-12, 1)
     assert np.allclose(P, [1.0 - 0.01, -2.0 + 0.01, 0.5 - 0.01], rtol=0, atol=1e-9)
+
+
+# ----------------------------------------------------------------------- stride labels (host logic)
+def test_stride_labels_pick_fastest_multiplier_per_bin():
+    from paper_1811_00009_amd import stride as stride_mod
+
+    def rows(m, rate):
+        out, b = [], 0.0
+        for k in range(20):
+            b += 0.01 * m
+            out.append({"feat": np.array([b] + [0.0] * 11, np.float32), "bound": b,
+                        "t_start": 0, "t_end": int(0.01 * m / rate * 1e8),
+                        "next_active": 1 if k < 19 else 0})
+        return out
+    traces = {0.5: rows(0.5, 1.0), 2.0: rows(2.0, 3.0), 8.0: rows(8.0, 2.0)}
+    X, y = stride_mod.label_traces(traces, nbins=4)
+    assert X.shape[1] == 12 and len(X) == len(y) == 57
+    # 2.0 has the highest progress rate wherever it has data
+    assert np.all(np.isclose(np.exp(y[X[:, 0] <= 0.4]), 2.0))
+    blob = stride_mod.pack_blob(stride_mod.init_params(0), np.zeros(12), np.ones(12))
+    assert blob.shape == (1505 + 24,) and blob.dtype == np.float32
