@@ -85,6 +85,9 @@ typedef struct {
     int32_t grid_limit;       /* persistent workgroups cap; 0 = occupancy-derived              */
     void *trace_dev;          /* nullable device buffer of trace_cap fmm_trace_row             */
     int32_t trace_cap;        /* rows available in trace_dev                                   */
+    int32_t band_lds_cap;     /* diagnostic: band slots kept in LDS while a block marches, a
+                                 multiple of 512; 0 = the default (1024); slots beyond it are
+                                 kept in device memory                                         */
 } fmm_options;
 
 /* Solve statistics (host struct, filled after the call). */

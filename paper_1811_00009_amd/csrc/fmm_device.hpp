@@ -81,6 +81,7 @@ struct KParams {
     void *trace;           // fmm_trace_row[trace_cap] or nullptr
     int32_t trace_cap;
     int32_t want_features; // accumulate restart features (trace or learned)
+    int32_t band_cap;      // diagnostic cap on band slots kept in LDS (0 = all that fit)
     int32_t *prob_lastr;   // [nprob] last restart in which the problem had work queued
     unsigned long long *prob_pops; // [nprob]
 };
@@ -92,12 +93,16 @@ struct KParams {
 // BAND slots (a multiple of 512) hold every point of the padded tile.  Tags are
 // padded to a multiple of 16 bytes.  For B <= 8 the block's h^2/F^2 values are
 // staged in LDS as well.
+// The first BANDC slots of the band stay in LDS while the block marches; the
+// rare slots beyond (a band larger than BANDC) are read and written in place in
+// the block's band array in device memory.
 template <int B>
 struct Geo {
     static constexpr int P = B + 2;
     static constexpr int T = P * P * P;
     static constexpr int B3 = B * B * B;
     static constexpr int BAND = (T + 511) / 512 * 512;
+    static constexpr int BANDC = BAND < 1024 ? BAND : 1024;
     static constexpr int TAGB = (T + 15) / 16 * 16;
     static constexpr bool RHS_LDS = B <= 8;
 };
@@ -107,7 +112,7 @@ struct Lds {
     static constexpr int T = Geo<B>::T;
     static constexpr size_t psi_off = 0;
     static constexpr size_t band_off = (psi_off + sizeof(R) * T + 15) / 16 * 16;
-    static constexpr size_t tag_off = band_off + 2 * Geo<B>::BAND;
+    static constexpr size_t tag_off = band_off + 2 * Geo<B>::BANDC;
     static constexpr size_t rhs_off = (tag_off + Geo<B>::TAGB + 15) / 16 * 16;
     static constexpr size_t scr_off = rhs_off + (Geo<B>::RHS_LDS ? sizeof(R) * T : 0);
     static constexpr size_t bytes = scr_off + 16 * 8 + 64;
@@ -214,8 +219,8 @@ struct MinPick {
 // minimum value first (high then low word for FP64), then the minimum key
 // among the lanes holding it.  Returns the same result in every lane.
 template <typename R, int W>
-__device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const R *s_psi, int n,
-                                                  char *scr)
+__device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const uint16_t *g_band,
+                                                  int cap, const R *s_psi, int n, char *scr)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const R inf = (R)INFINITY;
@@ -223,7 +228,8 @@ __device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const 
     uint32_t bk = ~0u;
     for (int c0 = wid * 512; c0 < n; c0 += 512 * W) {
         const int base = c0 + lane * 8;
-        const uint4 raw = *reinterpret_cast<const uint4 *>(s_band + base);
+        const uint4 raw = c0 < cap ? *reinterpret_cast<const uint4 *>(s_band + base)
+                                   : *reinterpret_cast<const uint4 *>(g_band + base);
         const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
         uint32_t ids[8];
         R vs[8];

@@ -305,6 +305,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     kp.trace = o.trace_dev;
     kp.trace_cap = o.trace_dev ? o.trace_cap : 0;
     kp.want_features = (kp.trace_cap > 0 || kp.stride_mode) ? 1 : 0;
+    kp.band_cap = o.band_lds_cap;
     kp.prob_lastr = (int32_t *)ws.plastr.p;
     kp.prob_pops = (unsigned long long *)ws.ppops.p;
 
@@ -427,6 +428,8 @@ int check_options(const fmm_options &o)
         return fail(FMM_EINVAL, "unknown launch_mode");
     if (o.trace_dev && o.trace_cap < 0) return fail(FMM_EINVAL, "trace_cap must be >= 0");
     if (o.max_restarts < 0) return fail(FMM_EINVAL, "max_restarts must be >= 0");
+    if (o.band_lds_cap < 0 || o.band_lds_cap % 512)
+        return fail(FMM_EINVAL, "band_lds_cap must be a non-negative multiple of 512");
     return 0;
 }
 

@@ -109,6 +109,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     using L = Lds<R, B, W>;
     using Gm = Geo<B>;
     constexpr int P = Gm::P, T = Gm::T, NT = 64 * W, BAND = Gm::BAND, TAGB = Gm::TAGB;
+    // band slots [0, cap) live in LDS, [cap, n) in the block's band array in memory
+    const int cap = kp.band_cap > 0 && kp.band_cap < Gm::BANDC ? kp.band_cap : Gm::BANDC;
     R *s_psi = reinterpret_cast<R *>(smem + L::psi_off);
     uint16_t *s_band = reinterpret_cast<uint16_t *>(smem + L::band_off);
     uint8_t *s_tag = reinterpret_cast<uint8_t *>(smem + L::tag_off);
@@ -126,7 +128,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(s_psi),
                                                reinterpret_cast<const uint4 *>(g_psi), tid);
     copy_vec16<NT, TAGB / 16>(reinterpret_cast<uint4 *>(s_tag), reinterpret_cast<const uint4 *>(g_tag), tid);
-    copy_band<NT>(s_band, g_band, n, tid);
+    copy_band<NT>(s_band, g_band, n < cap ? n : cap, tid);
     const R *rhs_src = g_rhs;
     if constexpr (Gm::RHS_LDS) {
         R *s_rhs = reinterpret_cast<R *>(smem + L::rhs_off);
@@ -150,7 +152,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             exit_min = inf;
             break;
         }
-        const MinPick<R> mp = band_argmin<R, W>(s_band, s_psi, n, scr);
+        const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n, scr);
         if ((double)mp.v > bound) {  // beyond the restart bound: stop (deactivate past width)
             if ((double)mp.v > pd.width) active = false;
             exit_min = mp.v;
@@ -175,10 +177,13 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             if (inb) rhs = rhs_src[q];
             const uint8_t tq = s_tag[q];  // lane 6 reads the accepted point's own tag
             const R psq = s_psi[q];
-            const uint16_t last = s_band[n];
+            const uint16_t last = n < cap ? s_band[n] : g_band[n];
             if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
                 s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
-            if (lane == 7) s_band[mp.slot] = last;
+            if (lane == 7) {
+                if (mp.slot < cap) s_band[mp.slot] = last;
+                else g_band[mp.slot] = last;
+            }
             bool ins = false;
             uint32_t fb = 0;
             if (inb && (tq & kStatus) != kKnownFix && psq > mp.v) {
@@ -202,8 +207,18 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 }
             }
             const uint64_t bal = ballot(ins);
-            if (ins) s_band[n + (int)lanes_below(bal)] = (uint16_t)q;
+            if (ins) {
+                const int at = n + (int)lanes_below(bal);
+                if (at < cap) s_band[at] = (uint16_t)q;
+                else g_band[at] = (uint16_t)q;
+            }
             n += (int)__popcll(bal);
+            if (n + 8 > cap) {
+                // the band reaches its memory part: make this wave's stores to it
+                // visible to its own later loads
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            }
 #pragma unroll
             for (int k = 0; k < 6; ++k) dirty |= (uint32_t)__builtin_amdgcn_readlane((int)fb, k);
             if constexpr (W > 1) {
@@ -225,7 +240,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(g_psi),
                                                reinterpret_cast<const uint4 *>(s_psi), tid);
     copy_vec16<NT, TAGB / 16>(reinterpret_cast<uint4 *>(g_tag), reinterpret_cast<const uint4 *>(s_tag), tid);
-    copy_band<NT>(g_band, s_band, n, tid);
+    copy_band<NT>(g_band, s_band, n < cap ? n : cap, tid);
     if (tid == 0) {
         kp.band_n[ib] = n;
         kp.A[ib] = active ? 1 : 0;

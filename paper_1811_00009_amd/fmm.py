@@ -41,7 +41,7 @@ class Options(C.Structure):
     _fields_ = [("width", C.c_double), ("stride_mode", C.c_int32), ("mlp_weights", C.c_void_p),
                 ("waves_per_block", C.c_int32), ("launch_mode", C.c_int32),
                 ("max_restarts", C.c_int64), ("grid_limit", C.c_int32),
-                ("trace_dev", C.c_void_p), ("trace_cap", C.c_int32)]
+                ("trace_dev", C.c_void_p), ("trace_cap", C.c_int32), ("band_lds_cap", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -152,7 +152,8 @@ def _sources(sources) -> "C.Array":
 
 
 def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_per_block=1,
-                 launch="persistent", max_restarts=0, grid_limit=0, trace=None) -> Options:
+                 launch="persistent", max_restarts=0, grid_limit=0, trace=None,
+                 band_lds_cap=0) -> Options:
     o = Options()
     load().fmm_options_default(C.byref(o))
     o.width = float(width)
@@ -164,6 +165,7 @@ def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_pe
     o.launch_mode = LAUNCH_HOST if launch == "host" else LAUNCH_PERSISTENT
     o.max_restarts = int(max_restarts)
     o.grid_limit = int(grid_limit)
+    o.band_lds_cap = int(band_lds_cap)
     if trace is not None:
         _check_tensor(trace, "trace")
         o.trace_dev = trace.data_ptr()

@@ -38,6 +38,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(fmm.Source) == 32
     assert C.sizeof(fmm.TraceRow) == 48 + 8 * 5 + 8
     assert C.sizeof(fmm.Stats) == 5 * 8 + 3 * 8 + 4 * 4
+    assert C.sizeof(fmm.Options) == 64
 
 
 def test_options_default():

@@ -216,3 +216,20 @@ def test_smooth_sine_256(fmm_lib, dtype):
     got, st = _run(fmm_lib, p, dtype, block=16)
     _assert_fp_parity(got, base, dtype)
     assert st["restarts"] >= np.max(base) / (2 * p.h)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_band_beyond_lds_capacity_spills_exactly(fmm_lib, dtype):
+    """Band slots past the LDS capacity live in device memory; forcing a small capacity
+    (512 slots) must not change a single bit or count."""
+    p = inputs.random_problem(350, shape=(32, 48, 32), nsrc=6, dtype=dtype, obstacles=0.01)
+    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=16, stride=3.5 * p.h, dtype=dtype,
+                               stats=True)
+    for cap in (512, 0):
+        got, st = _run(fmm_lib, p, dtype, block=16, stride=3.5 * p.h, band_lds_cap=cap)
+        assert np.array_equal(got, ref)
+        assert st["pops"] == rs["pops"] and st["restarts"] == rs["restarts"]
+    wide = inputs.smooth_sine(64, dtype=dtype)
+    ref = oracle.block_fmm(wide.F, wide.h, wide.sources, block=16, stride=8 * wide.h, dtype=dtype)
+    got, _ = _run(fmm_lib, wide, dtype, block=16, stride=8 * wide.h, band_lds_cap=512)
+    assert np.array_equal(got, ref)
