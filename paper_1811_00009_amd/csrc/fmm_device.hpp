@@ -18,6 +18,11 @@
 
 namespace fmmdev {
 
+// Pointers into the work-group's LDS carry the LDS address space, so every access
+// through them is a ds_* instruction (never a flat access).
+#define FMM_LDS __attribute__((address_space(3)))
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));  // 16-byte copy unit
+
 // ---------------------------------------------------------------- tags
 // bits 0-1: category (Sec. 2.1 with KNOWN split as in Sec. 2.2); bit 2: the
 // point currently sits in the block's band array.
@@ -35,6 +40,7 @@ struct Ctl {
     int pad0;
     int n_list[2];                 // march-list sizes, by restart parity
     int q_head[2];                 // march work-queue heads, by restart parity
+    int bin_n[2][4];               // march-list sizes per work bin, by restart parity
     unsigned long long pops, march_calls, exchange_calls, tile_loads;
     unsigned long long rpops[2];   // pops of the current restart, by parity
     unsigned long long feat[2][10];// band-size bins (8), sum of block mean speed (2^20 fixed
@@ -68,7 +74,8 @@ struct KParams {
     uint32_t *Cm;          // [nblk] exchange flags C, one bit per face (Sec. 2.6)
     int32_t *blk_prob;     // [nblk] problem of each block
     float *fmean;          // [nblk] mean speed of the block's interior
-    int32_t *list0, *list1;// march lists, by restart parity
+    int32_t *lastpops;     // [nblk] pops of the block's last march (work estimate)
+    int32_t *list0, *list1;// march lists, by restart parity; 4 bins of nblk entries each
     Ctl *ctl;
     const ProbDesc *prob;
     int32_t nprob;
@@ -120,14 +127,14 @@ struct Lds {
 
 // Copy NVEC 16-byte vectors global -> LDS (or back), eight per thread in flight
 // before the first wait.
-template <int NT, int NVEC>
-__device__ __forceinline__ void copy_vec16(uint4 *__restrict__ dst, const uint4 *__restrict__ src, int tid)
+template <int NT, int NVEC, typename D, typename S>
+__device__ __forceinline__ void copy_vec16(D *__restrict__ dst, const S *__restrict__ src, int tid)
 {
     constexpr int PER = (NVEC + NT - 1) / NT;
     constexpr int BATCH = 8;
 #pragma unroll
     for (int b0 = 0; b0 < PER; b0 += BATCH) {
-        uint4 r[BATCH];
+        v4u r[BATCH];
 #pragma unroll
         for (int j = 0; j < BATCH; ++j) {
             const int i = tid + (b0 + j) * NT;
@@ -142,22 +149,22 @@ __device__ __forceinline__ void copy_vec16(uint4 *__restrict__ dst, const uint4 
 }
 
 // Copy the first n entries (rounded up to 8) of a band array.
-template <int NT>
-__device__ __forceinline__ void copy_band(uint16_t *dst, const uint16_t *src, int n, int tid)
+template <int NT, typename D, typename S>
+__device__ __forceinline__ void copy_band(D *dst, const S *src, int n, int tid)
 {
     const int nvec = (n + 7) >> 3;
     for (int v0 = 0; v0 < nvec; v0 += 4 * NT) {
-        uint4 r[4];
+        v4u r[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             int v = v0 + tid + j * NT;
             v = v < nvec ? v : nvec - 1;  // clamped: always in bounds
-            r[j] = reinterpret_cast<const uint4 *>(src)[v];
+            r[j] = reinterpret_cast<const S *>(src)[v];
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int v = v0 + tid + j * NT;
-            if (v < nvec) reinterpret_cast<uint4 *>(dst)[v] = r[j];
+            if (v < nvec) reinterpret_cast<D *>(dst)[v] = r[j];
         }
     }
 }
@@ -219,8 +226,9 @@ struct MinPick {
 // minimum value first (high then low word for FP64), then the minimum key
 // among the lanes holding it.  Returns the same result in every lane.
 template <typename R, int W>
-__device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const uint16_t *g_band,
-                                                  int cap, const R *s_psi, int n, char *scr)
+__device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band,
+                                                  const uint16_t *g_band, int cap,
+                                                  const FMM_LDS R *s_psi, int n)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const R inf = (R)INFINITY;
@@ -228,8 +236,18 @@ __device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const 
     uint32_t bk = ~0u;
     for (int c0 = wid * 512; c0 < n; c0 += 512 * W) {
         const int base = c0 + lane * 8;
-        const uint4 raw = c0 < cap ? *reinterpret_cast<const uint4 *>(s_band + base)
-                                   : *reinterpret_cast<const uint4 *>(g_band + base);
+        v4u raw;
+        if (c0 < cap) {
+            raw = *reinterpret_cast<const FMM_LDS v4u *>(s_band + base);
+        } else {
+            // the band's memory part (nontemporal loads: never merged with the LDS
+            // path into one flat access)
+            const uint32_t *g = reinterpret_cast<const uint32_t *>(g_band + base);
+            raw.x = __builtin_nontemporal_load(g);
+            raw.y = __builtin_nontemporal_load(g + 1);
+            raw.z = __builtin_nontemporal_load(g + 2);
+            raw.w = __builtin_nontemporal_load(g + 3);
+        }
         const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
         uint32_t ids[8];
         R vs[8];
@@ -263,7 +281,7 @@ __device__ __forceinline__ MinPick<R> band_argmin(const uint16_t *s_band, const 
     uint32_t mk = wave_min_u32(tie ? bk : ~0u);
     uint32_t h = mh, l = ml;
     if constexpr (W > 1) {
-        uint32_t *s = reinterpret_cast<uint32_t *>(scr);
+        __shared__ uint32_t s[16];
         if (lane == 0) {
             s[4 * wid + 0] = mh;
             s[4 * wid + 1] = ml;

@@ -71,8 +71,8 @@ int ensure(DevBuf &b, size_t bytes, const char *what)
 
 // Library-owned device memory of one GPU, grown on demand and kept for reuse.
 struct Workspace {
-    DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, list0, list1, ctl, prob, src,
-        plastr, ppops;
+    DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, lastpops, list0, list1, ctl, prob,
+        src, plastr, ppops;
     hipEvent_t e0 = nullptr, e1 = nullptr, l0 = nullptr, l1 = nullptr;
 };
 
@@ -247,8 +247,9 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
         (rc = ensure(ws.Cm, (size_t)nblk * 4, "exchange flags")) ||
         (rc = ensure(ws.bprob, (size_t)nblk * 4, "block problems")) ||
         (rc = ensure(ws.fmean, (size_t)nblk * 4, "block speeds")) ||
-        (rc = ensure(ws.list0, (size_t)nblk * 4, "march list 0")) ||
-        (rc = ensure(ws.list1, (size_t)nblk * 4, "march list 1")) ||
+        (rc = ensure(ws.lastpops, (size_t)nblk * 4, "block work estimates")) ||
+        (rc = ensure(ws.list0, (size_t)nblk * 4 * 4, "march list 0")) ||
+        (rc = ensure(ws.list1, (size_t)nblk * 4 * 4, "march list 1")) ||
         (rc = ensure(ws.ctl, sizeof(Ctl), "control block")) ||
         (rc = ensure(ws.prob, sizeof(ProbDesc) * nprob, "problem table")) ||
         (rc = ensure(ws.plastr, sizeof(int32_t) * nprob, "problem restarts")) ||
@@ -271,7 +272,8 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     for (int32_t q = 0; q < nprob; ++q) descs[q] = probs[q].d;
     Ctl hc;
     std::memset(&hc, 0, sizeof(hc));
-    hc.n_list[1] = (int)first.size();  // restart 1 marches list[1]
+    hc.n_list[1] = (int)first.size();  // restart 1 marches list[1] (all in bin 0)
+    hc.bin_n[1][0] = (int)first.size();
 
     HIPCHK(hipMemcpyAsync(ws.prob.p, descs.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ws.src.p, ents.data(), sizeof(SrcEntry) * ents.size(), hipMemcpyHostToDevice, st));
@@ -291,6 +293,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     kp.Cm = (uint32_t *)ws.Cm.p;
     kp.blk_prob = (int32_t *)ws.bprob.p;
     kp.fmean = (float *)ws.fmean.p;
+    kp.lastpops = (int32_t *)ws.lastpops.p;
     kp.list0 = (int32_t *)ws.list0.p;
     kp.list1 = (int32_t *)ws.list1.p;
     kp.ctl = (Ctl *)ws.ctl.p;

@@ -111,11 +111,11 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     constexpr int P = Gm::P, T = Gm::T, NT = 64 * W, BAND = Gm::BAND, TAGB = Gm::TAGB;
     // band slots [0, cap) live in LDS, [cap, n) in the block's band array in memory
     const int cap = kp.band_cap > 0 && kp.band_cap < Gm::BANDC ? kp.band_cap : Gm::BANDC;
-    R *s_psi = reinterpret_cast<R *>(smem + L::psi_off);
-    uint16_t *s_band = reinterpret_cast<uint16_t *>(smem + L::band_off);
-    uint8_t *s_tag = reinterpret_cast<uint8_t *>(smem + L::tag_off);
-    char *scr = smem + L::scr_off;
-    int *s_bc = reinterpret_cast<int *>(scr + 64);
+    FMM_LDS char *lds = (FMM_LDS char *)smem;
+    FMM_LDS R *s_psi = reinterpret_cast<FMM_LDS R *>(lds + L::psi_off);
+    FMM_LDS uint16_t *s_band = reinterpret_cast<FMM_LDS uint16_t *>(lds + L::band_off);
+    FMM_LDS uint8_t *s_tag = reinterpret_cast<FMM_LDS uint8_t *>(lds + L::tag_off);
+    __shared__ int s_bc[1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const R inf = (R)INFINITY;
 
@@ -125,17 +125,16 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     const R *g_rhs = kp.rhs_t + ib * (int64_t)T;
 
     int n = kp.band_n[ib];
-    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(s_psi),
-                                               reinterpret_cast<const uint4 *>(g_psi), tid);
-    copy_vec16<NT, TAGB / 16>(reinterpret_cast<uint4 *>(s_tag), reinterpret_cast<const uint4 *>(g_tag), tid);
-    copy_band<NT>(s_band, g_band, n < cap ? n : cap, tid);
-    const R *rhs_src = g_rhs;
-    if constexpr (Gm::RHS_LDS) {
-        R *s_rhs = reinterpret_cast<R *>(smem + L::rhs_off);
-        copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(s_rhs),
-                                                   reinterpret_cast<const uint4 *>(g_rhs), tid);
-        rhs_src = s_rhs;
-    }
+    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_psi),
+                                               reinterpret_cast<const v4u *>(g_psi), tid);
+    copy_vec16<NT, TAGB / 16>(reinterpret_cast<FMM_LDS v4u *>(s_tag),
+                              reinterpret_cast<const v4u *>(g_tag), tid);
+    copy_band<NT>(reinterpret_cast<FMM_LDS v4u *>(s_band), reinterpret_cast<const v4u *>(g_band),
+                  n < cap ? n : cap, tid);
+    FMM_LDS R *s_rhs = reinterpret_cast<FMM_LDS R *>(lds + L::rhs_off);
+    if constexpr (Gm::RHS_LDS)
+        copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_rhs),
+                                                   reinterpret_cast<const v4u *>(g_rhs), tid);
     __syncthreads();
 
     // per-lane neighbour direction of Update_Neighbors: lanes 0-5 = -x, +x, -y, +y, -z, +z
@@ -152,7 +151,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             exit_min = inf;
             break;
         }
-        const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n, scr);
+        const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n);
         if ((double)mp.v > bound) {  // beyond the restart bound: stop (deactivate past width)
             if ((double)mp.v > pd.width) active = false;
             exit_min = mp.v;
@@ -174,15 +173,20 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                              (unsigned)(qj - 1) < (unsigned)B && (unsigned)(qk - 1) < (unsigned)B;
             const int q = inb ? p + dOff : p;
             R rhs = (R)0;
-            if (inb) rhs = rhs_src[q];
+            if (inb) {
+                if constexpr (Gm::RHS_LDS) rhs = s_rhs[q];
+                else rhs = g_rhs[q];
+            }
             const uint8_t tq = s_tag[q];  // lane 6 reads the accepted point's own tag
             const R psq = s_psi[q];
-            const uint16_t last = n < cap ? s_band[n] : g_band[n];
+            uint16_t last;
+            if (n < cap) last = s_band[n];
+            else last = __builtin_nontemporal_load(g_band + n);
             if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
                 s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
             if (lane == 7) {
                 if (mp.slot < cap) s_band[mp.slot] = last;
-                else g_band[mp.slot] = last;
+                else __builtin_nontemporal_store(last, g_band + mp.slot);
             }
             bool ins = false;
             uint32_t fb = 0;
@@ -210,7 +214,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             if (ins) {
                 const int at = n + (int)lanes_below(bal);
                 if (at < cap) s_band[at] = (uint16_t)q;
-                else g_band[at] = (uint16_t)q;
+                else __builtin_nontemporal_store((uint16_t)q, g_band + at);
             }
             n += (int)__popcll(bal);
             if (n + 8 > cap) {
@@ -237,14 +241,17 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     }
 
     // LDS -> tile
-    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<uint4 *>(g_psi),
-                                               reinterpret_cast<const uint4 *>(s_psi), tid);
-    copy_vec16<NT, TAGB / 16>(reinterpret_cast<uint4 *>(g_tag), reinterpret_cast<const uint4 *>(s_tag), tid);
-    copy_band<NT>(g_band, s_band, n < cap ? n : cap, tid);
+    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<v4u *>(g_psi),
+                                               reinterpret_cast<const FMM_LDS v4u *>(s_psi), tid);
+    copy_vec16<NT, TAGB / 16>(reinterpret_cast<v4u *>(g_tag),
+                              reinterpret_cast<const FMM_LDS v4u *>(s_tag), tid);
+    copy_band<NT>(reinterpret_cast<v4u *>(g_band), reinterpret_cast<const FMM_LDS v4u *>(s_band),
+                  n < cap ? n : cap, tid);
     if (tid == 0) {
         kp.band_n[ib] = n;
         kp.A[ib] = active ? 1 : 0;
         kp.bmin[ib] = exit_min;
+        kp.lastpops[ib] = (int32_t)npops;
     }
     // C^nb(ib) <- TRUE for the neighbours whose ghosts meet Upsilon^ib
     if (tid < 6 && ((dirty >> tid) & 1u)) {
@@ -283,9 +290,9 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
     constexpr int P = Geo<B>::P, T = Geo<B>::T, NT = 64 * W, FB = B * B, BAND = Geo<B>::BAND,
                   TAGB = Geo<B>::TAGB;
     const int tid = threadIdx.x;
-    int *s_cnt = reinterpret_cast<int *>(smem + L::scr_off + 64);
+    __shared__ int s_cnt[1];
     using U = typename std::conditional<sizeof(R) == 4, uint32_t, unsigned long long>::type;
-    U *s_min = reinterpret_cast<U *>(smem + L::scr_off + 80);
+    __shared__ U s_min[1];
     if (tid == 0) {
         s_cnt[0] = 0;
         const R inf = (R)INFINITY;
@@ -341,7 +348,7 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
     }
     if (my_min != ~(U)0) atomicMin(s_min, my_min);
     __syncthreads();
-    int *s_res = reinterpret_cast<int *>(smem + L::scr_off + 72);
+    __shared__ int s_res[2];
     if (tid == 0) {
         const int nn = n0 + s_cnt[0];
         R cmin;
@@ -366,7 +373,10 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
 
 // ---------------------------------------------------------------- phase drivers
 // Marching step of restart r: blocks of the march list list[r & 1] are taken
-// from a work queue.  A block whose exact band minimum is above its bound is
+// from a work queue, longest expected march first: the list is binned when it
+// is built by the pops of each block's previous march (blocks without one go
+// first), a cheap longest-job-first order that shortens the wait for the
+// slowest block at the barrier.  A block whose exact band minimum is above its bound is
 // not loaded: Alg. 4 would stop at once without changing anything (only the
 // width test can flip its activation).
 template <typename R, int B, int W>
@@ -378,7 +388,11 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
     Ctl *ctl = kp.ctl;
     const int32_t *cur = c ? kp.list1 : kp.list0;
     const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    int *s_item = reinterpret_cast<int *>(smem + L::scr_off + 96);
+    __shared__ int s_bins[3];
+    if (tid < 3) s_bins[tid] = __hip_atomic_load(&ctl->bin_n[c][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int bn0 = s_bins[0], bn1 = s_bins[1], bn2 = s_bins[2];
+    __shared__ int s_item[1];
     unsigned long long pops = 0, mcalls = 0, loads = 0;
     for (;;) {
         if (tid == 0) s_item[0] = atomicAdd(&ctl->q_head[c], 1);
@@ -386,7 +400,21 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         const int item = s_item[0];
         __syncthreads();
         if (item >= ncur) break;
-        const int64_t ib = cur[item];
+        // bins in order: the blocks with the largest bands (the longest marches) first
+        int k = 0, off = item;
+        if (off >= bn0) {
+            off -= bn0;
+            k = 1;
+            if (off >= bn1) {
+                off -= bn1;
+                k = 2;
+                if (off >= bn2) {
+                    off -= bn2;
+                    k = 3;
+                }
+            }
+        }
+        const int64_t ib = cur[(int64_t)k * kp.nblk + off];
         const ProbDesc pd = kp.nprob == 1 ? kp.prob[0] : kp.prob[kp.blk_prob[ib]];
         const double bound = kp.stride_mode ? lbound : fixed_bound(r, pd.stride, pd.width);
         ++mcalls;
@@ -426,6 +454,7 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
         const uint32_t cm = valid ? kp.Cm[ib] : 0u;
         bool a = valid ? (kp.A[ib] != 0) : false;
         int nb = valid ? kp.band_n[ib] : 0;
+        const int lp = valid ? kp.lastpops[ib] : 0;
         uint64_t em = ballot(cm != 0u);
         while (em) {
             const int l = __ffsll((long long)em) - 1;
@@ -445,10 +474,18 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
         if (wid == 0) {
             const uint64_t am = ballot(a);
             if (am) {
-                int pos0 = 0;
-                if (lane == 0) pos0 = atomicAdd(&ctl->n_list[c ^ 1], (int)__popcll(am));
-                pos0 = __builtin_amdgcn_readfirstlane(pos0);
-                if (a) next[pos0 + (int)lanes_below(am)] = (int32_t)ib;
+                if (lane == 0) atomicAdd(&ctl->n_list[c ^ 1], (int)__popcll(am));
+                const int wbin = lp >= 768 ? 0 : (lp >= 256 ? 1 : (lp >= 64 ? 2 : 3));
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint64_t mk = ballot(a && wbin == k);
+                    if (!mk) continue;
+                    int pos0 = 0;
+                    if (lane == 0) pos0 = atomicAdd(&ctl->bin_n[c ^ 1][k], (int)__popcll(mk));
+                    pos0 = __builtin_amdgcn_readfirstlane(pos0);
+                    if (a && wbin == k)
+                        next[(int64_t)k * kp.nblk + pos0 + (int)lanes_below(mk)] = (int32_t)ib;
+                }
                 if (kp.want_features) {
                     int bin = 0;
                     if (nb >= 1) bin = 1;
@@ -535,6 +572,7 @@ __global__ void __launch_bounds__(64 * W) k_persistent(KParams<R> kp)
             ctl->n_list[c ^ 1] = 0;
             ctl->q_head[c ^ 1] = 0;
             ctl->rpops[c ^ 1] = 0;
+            for (int k = 0; k < 4; ++k) ctl->bin_n[c ^ 1][k] = 0;
             for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
             t0 = wall_ticks();
         }
@@ -599,6 +637,7 @@ __global__ void k_restart_prologue(KParams<R> kp, int64_t r)
     ctl->n_list[c ^ 1] = 0;
     ctl->q_head[c ^ 1] = 0;
     ctl->rpops[c ^ 1] = 0;
+    for (int k = 0; k < 4; ++k) ctl->bin_n[c ^ 1][k] = 0;
     for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
 }
 
@@ -661,6 +700,7 @@ __global__ void __launch_bounds__(256) k_init(KParams<R> kp)
             kp.A[ib] = 0;
             kp.Cm[ib] = 0u;
             kp.bmin[ib] = (R)INFINITY;
+            kp.lastpops[ib] = 1 << 20;  // no history yet: schedule early
         }
         __syncthreads();
     }
