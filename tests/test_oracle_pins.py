@@ -385,3 +385,29 @@ def test_stride_labels_pick_fastest_multiplier_per_bin():
     assert np.all(np.isclose(np.exp(y[X[:, 0] <= 0.4]), 2.0))
     blob = stride_mod.pack_blob(stride_mod.init_params(0), np.zeros(12), np.ones(12))
     assert blob.shape == (1505 + 24,) and blob.dtype == np.float32
+
+
+# ------------------------------------------------------------------ box restriction
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_box_restriction_is_exact_below_boundary_layer_minimum(seed):
+    """The full-size parity check compares a large solve with the oracle on a box around the
+    source; the points it keeps must have exactly the whole-grid values (bitwise, both
+    precisions), and the region must not be trivial."""
+    from boxcut import box_origin, box_slices, exact_region
+    rng = np.random.default_rng(seed)
+    shape = (40, 48, 56)
+    for dtype in (np.float64, np.float32):
+        F = rng.uniform(0.3, 2.0, size=shape).astype(dtype)
+        src = (int(rng.integers(4, 52)), int(rng.integers(4, 44)), int(rng.integers(4, 36)))
+        h = 1.0 / 55
+        full = oracle.fmm(F, h, [src + (0.0,)], dtype=dtype)
+        box = 24
+        lo = box_origin(src, shape, box)
+        sub = np.ascontiguousarray(F[box_slices(lo, box)])
+        ref = oracle.fmm(sub, h, [(src[0] - lo[0], src[1] - lo[1], src[2] - lo[2], 0.0)],
+                         dtype=dtype)
+        keep = exact_region(ref, lo, shape)
+        assert keep.sum() > 500
+        assert np.array_equal(ref[keep], full[box_slices(lo, box)][keep])
+        # just past the region the restriction is no longer exact somewhere (the check is sharp)
+        assert not np.array_equal(ref, full[box_slices(lo, box)])
