@@ -8,11 +8,18 @@ psi and F, 16^3 blocks, fixed stride 2h.  One step = one full solve (layout,
 initialisation, every restart of the persistent kernel, copy back) with F
 already resident in HBM.
 
+Other workloads (--workload): smooth_sine_256_f32/_f64, smooth_point_64, and
+batched_512 (512 solves of uneven sizes with Fourier speeds, one persistent
+launch with the autotuned block size and waves per block, against 512
+sequential solves).
+
 Prints ONE JSON line.  Besides the contract fields it carries
   roofline      HBM roofline of the dominant kernel (the persistent restart loop)
   cpu_baseline  the CPU oracle (single-heap FMM, one thread) timed on a bounded
                 sample of the same workload on this host
-  extra         restarts, pops, pops/s, device times, launch shape
+  extra         restarts, pops, pops/s, device times, launch shape; for the
+                default workload also the same solve with the learned stride
+                (when trained weights are present) and with 8^3 blocks
 """
 import argparse
 import hashlib
@@ -59,11 +66,7 @@ def build_workload(name, torch):
     from paper_1811_00009_amd import inputs
     if name == "coarse_cells_1024":
         p = inputs.coarse_cells(1024, 64, seed=(3,), materialize=False)
-        V = torch.from_numpy(p.meta["V"].astype(np.float32)).cuda()
-        n, c = 1024, 64
-        r = n // c
-        F = V[:, None, :, None, :, None].expand(c, r, c, r, c, r).reshape(n, n, n).contiguous()
-        return p, F, "f32"
+        return p, inputs.expand_cells_device(p.meta["V"], 1024, torch), "f32"
     if name == "smooth_sine_256_f32":
         p = inputs.smooth_sine(256, dtype=np.float32)
         return p, torch.from_numpy(p.F).cuda(), "f32"
@@ -106,7 +109,39 @@ def cpu_baseline(p, workload, seconds_target=15.0):
                       f"the same speed field ({pts} points, {dt:.1f} s, one thread)"}
 
 
-def main():
+WEIGHTS = os.path.join(ROOT, "paper_1811_00009_amd", "weights", "stride_mlp_b16.f32")
+
+
+def load_weights(torch):
+    """Trained stride-network blob (parameters, feature mean and std) on the device, or None."""
+    import numpy as np
+    if not os.path.exists(WEIGHTS):
+        return None
+    blob = np.fromfile(WEIGHTS, dtype="<f4")
+    return torch.from_numpy(blob).cuda()
+
+
+def timed(fn, steps, warmup, label):
+    import torch
+    for w in range(warmup):
+        st = fn()
+        print(f"[bench] {label} warmup {w}: {st['elapsed_ms']:.1f} ms device", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(fn())
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for k, st in enumerate(stats):
+        print(f"[bench] {label} step {k}: {st['elapsed_ms']:.1f} ms device, loop "
+              f"{st['loop_ms']:.1f} ms, {st['restarts']} restarts, {st['pops']} pops",
+              file=sys.stderr, flush=True)
+    return stats, wall
+
+
+def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -116,24 +151,32 @@ def main():
     ap.add_argument("--waves", type=int, default=1)
     ap.add_argument("--stride-h", type=float, default=2.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned-stride and 8^3-block solves of the default workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    args = ap.parse_args()
+    return ap.parse_args()
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the multi-GPU sharding of the block grid is a design, not part of this build)",
-              file=sys.stderr)
-        sys.exit(2)
 
-    import torch
-    from paper_1811_00009_amd import fmm
-    fmm.load()
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+def roofline(dtype, npts, loop_ms, workload):
+    algo_bytes = ALGO_BYTES_PER_POINT[dtype] * npts
+    achieved = algo_bytes / (loop_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+            "traffic": measured_traffic(workload, npts),
+            "kernel": "k_persistent (restart loop)",
+            "algorithmic_bytes_per_launch": algo_bytes,
+            "kernel_ms": round(loop_ms, 3)}
 
+
+def contract(args, value, ms_per_step, dtype, config):
+    return {"metric": METRIC, "value": round(value, 3), "unit": "Mpts/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+            "data": "synthetic", "config": config}
+
+
+def run_single(args, torch, fmm):
     p, F, dtype = build_workload(args.workload, torch)
     nz, ny, nx = F.shape
     npts = nx * ny * nz
@@ -147,26 +190,13 @@ def main():
         return fmm.solve(F, p.h, p.sources, block=args.block, stride=stride, out=psi,
                          with_stats=True, waves_per_block=args.waves)[1]
 
-    for w in range(args.warmup):
-        st = step()
-        print(f"[bench] warmup {w}: {st['elapsed_ms']:.1f} ms device, {st['restarts']} restarts",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        stats.append(step())
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for k, st in enumerate(stats):
-        print(f"[bench] step {k}: {st['elapsed_ms']:.1f} ms device, loop {st['loop_ms']:.1f} ms, "
-              f"{st['restarts']} restarts, {st['pops']} pops", file=sys.stderr, flush=True)
-
+    stats, wall = timed(step, args.steps, args.warmup, "fixed")
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
 
     # sanity of the output: every point reached, zero at the source
     s0 = p.sources[0]
@@ -177,42 +207,141 @@ def main():
     value = npts / (ms_per_step / 1e3) / 1e6
     loop_ms = sum(s["loop_ms"] for s in stats) / len(stats)
     dev_ms = sum(s["elapsed_ms"] for s in stats) / len(stats)
-    algo_bytes = ALGO_BYTES_PER_POINT[dtype] * npts
-    achieved = algo_bytes / (loop_ms / 1e3) / 1e9
-    traffic = measured_traffic(args.workload, npts)
     st = stats[-1]
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Mpts/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": dtype,
-        "data": "synthetic",
-        "config": {"workload": args.workload, "grid": [nx, ny, nz], "h": p.h, "block": args.block,
-                   "waves_per_block": args.waves, "stride_h": args.stride_h,
-                   "sources": [list(s[:3]) for s in p.sources], "stride_mode": "fixed"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic,
-                     "kernel": "k_persistent (restart loop)",
-                     "algorithmic_bytes_per_launch": algo_bytes,
-                     "kernel_ms": round(loop_ms, 3)},
-        "extra": {"restarts": st["restarts"], "pops": st["pops"],
-                  "pops_per_s": round(st["pops"] / (st["loop_ms"] / 1e3), 1),
-                  "march_calls": st["march_calls"], "tile_loads": st["tile_loads"],
-                  "exchange_calls": st["exchange_calls"], "device_ms": round(dev_ms, 3),
-                  "loop_ms": round(loop_ms, 3), "grid": st["grid"],
-                  "device_Mpts_per_s": round(npts / (dev_ms / 1e3) / 1e6, 3),
-                  "kernel_hash": kernel_source_hash()},
-    }
+    out = contract(args, value, ms_per_step, dtype,
+                   {"workload": args.workload, "grid": [nx, ny, nz], "h": p.h,
+                    "block": args.block, "waves_per_block": args.waves,
+                    "stride_h": args.stride_h, "sources": [list(s[:3]) for s in p.sources],
+                    "stride_mode": "fixed"})
+    out["roofline"] = roofline(dtype, npts, loop_ms, args.workload)
+    out["extra"] = {"restarts": st["restarts"], "pops": st["pops"],
+                    "pops_per_s": round(st["pops"] / (st["loop_ms"] / 1e3), 1),
+                    "march_calls": st["march_calls"], "tile_loads": st["tile_loads"],
+                    "exchange_calls": st["exchange_calls"], "device_ms": round(dev_ms, 3),
+                    "loop_ms": round(loop_ms, 3), "grid": st["grid"],
+                    "device_Mpts_per_s": round(npts / (dev_ms / 1e3) / 1e6, 3),
+                    "kernel_hash": kernel_source_hash()}
+
+    if args.workload == "coarse_cells_1024" and not args.no_extras:
+        fixed = psi.clone()
+        tol = 1e-5 * float(fixed.max())
+        blob = load_weights(torch)
+        if blob is not None:
+            out2 = torch.empty_like(F)
+            ls, lwall = timed(lambda: fmm.solve(F, p.h, p.sources, block=args.block,
+                                                stride=stride, out=out2, with_stats=True,
+                                                stride_mode="learned", mlp_weights=blob)[1],
+                              1, 1, "learned")
+            diff = float((out2 - fixed).abs().max())
+            out["extra"]["learned_stride"] = {
+                "Mpts_per_s": round(npts / lwall / 1e6, 3),
+                "vs_fixed_2h": round((npts / lwall / 1e6) / value, 4),
+                "restarts": ls[-1]["restarts"], "pops": ls[-1]["pops"],
+                "final_bound": ls[-1]["final_bound"],
+                "max_abs_diff_vs_fixed": diff, "within_fp32_bar": diff <= tol,
+                "weights": os.path.relpath(WEIGHTS, ROOT)}
+            del out2
+        out8 = torch.empty_like(F)
+        bs, bwall = timed(lambda: fmm.solve(F, p.h, p.sources, block=8, stride=stride, out=out8,
+                                            with_stats=True)[1], 1, 1, "block8")
+        diff = float((out8 - fixed).abs().max())
+        out["extra"]["block8"] = {"Mpts_per_s": round(npts / bwall / 1e6, 3),
+                                  "pops": bs[-1]["pops"], "grid": bs[-1]["grid"],
+                                  "max_abs_diff_vs_block16": diff, "within_fp32_bar": diff <= tol}
+        del out8, fixed
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.workload)
+    return out
+
+
+def run_batched(args, torch, fmm):
+    """512 solves of uneven sizes: one persistent launch (autotuned) vs 512 plain launches."""
+    from paper_1811_00009_amd import inputs
+    nsolve = 512
+    t0 = time.perf_counter()
+    probs = [inputs.batched_problem_device(s, torch) for s in range(nsolve)]
+    torch.cuda.synchronize()
+    npts = sum(int(p.F.numel()) for p in probs)
+    print(f"[bench] batched_512: {nsolve} fields, {npts} points, built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    tune = fmm.autotune([(p.F, p.h, p.sources) for p in probs[:8]])
+    print(f"[bench] autotuned on 8 sample fields: block {tune['block']}, waves "
+          f"{tune['waves_per_block']}", file=sys.stderr, flush=True)
+    B, W = tune["block"], tune["waves_per_block"]
+    batch = [(p.F, p.h, p.sources) for p in probs]
+    outs = [torch.empty_like(p.F) for p in probs]
+
+    def step():
+        return fmm.solve_batched(batch, block=B, waves_per_block=W, outs=outs,
+                                 with_stats=True)[1][0]
+
+    stats, wall = timed(step, args.steps, args.warmup, "batched")
+    ms_per_step = wall / args.steps * 1e3
+    value = npts / (ms_per_step / 1e3) / 1e6
+    loop_ms = sum(s["loop_ms"] for s in stats) / len(stats)
+    # the same 512 solves as separate plain launches (same block size, default stride)
+    seq_out = [torch.empty_like(p.F) for p in probs]
+    for p, o in zip(probs[:4], seq_out):
+        fmm.solve(p.F, p.h, p.sources, block=B, waves_per_block=W, out=o)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p, o in zip(probs, seq_out):
+        fmm.solve(p.F, p.h, p.sources, block=B, waves_per_block=W, out=o)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    same = all(torch.equal(a, b) for a, b in zip(outs, seq_out))
+    print(f"[bench] sequential: {seq * 1e3:.1f} ms for {nsolve} launches; identical: {same}",
+          file=sys.stderr, flush=True)
+    out = contract(args, value, ms_per_step, "f32",
+                   {"workload": "batched_512", "solves": nsolve, "points": npts,
+                    "sides": "uniform over {32, 48, ..., 192}", "block": B, "waves_per_block": W,
+                    "stride_h": 2.0, "stride_mode": "fixed", "tuned_on": "fields 0-7"})
+    out["roofline"] = roofline("f32", npts, loop_ms, "batched_512")
+    out["extra"] = {"sequential_Mpts_per_s": round(npts / seq / 1e6, 3),
+                    "batched_over_sequential": round(seq / (wall / args.steps), 3),
+                    "identical_to_sequential": same, "loop_ms": round(loop_ms, 3),
+                    "grid": stats[-1]["grid"], "kernel_hash": kernel_source_hash()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batched()
+    return out
+
+
+def cpu_baseline_batched(seconds_target=12.0):
+    """Oracle (one thread, FP64) on the batched fields in order until ~seconds_target."""
+    import numpy as np
+    import oracle
+    from paper_1811_00009_amd import inputs
+    pts, dt, k = 0, 0.0, 0
+    while dt < seconds_target and k < 512:
+        p = inputs.batched_problem(k, dtype=np.float64)
+        t0 = time.perf_counter()
+        oracle.fmm(p.F, p.h, p.sources)
+        dt += time.perf_counter() - t0
+        pts += p.F.size
+        k += 1
+    return {"value": round(pts / dt / 1e6, 4), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+            "sample": f"single-heap FMM in FP64 on batched fields 0-{k - 1} ({pts} points, "
+                      f"{dt:.1f} s, one thread)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
+              "(the multi-GPU sharding of the block grid is a design, not part of this build)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1811_00009_amd import fmm
+    fmm.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    torch.cuda.set_device(torch.device("cuda:0"))
+    if args.workload == "batched_512":
+        out = run_batched(args, torch, fmm)
+    else:
+        out = run_single(args, torch, fmm)
     print(json.dumps(out), flush=True)
 
 

@@ -119,6 +119,8 @@ typedef struct {
     int64_t t_end;           /* and at its end                                             */
     int32_t active;          /* blocks in the march list of this restart                   */
     int32_t next_active;     /* blocks in the march list of the next restart               */
+    double min_popped;       /* smallest value accepted (popped) in this restart; +inf when
+                                none: a value below an earlier bound marks a late correction */
 } fmm_trace_row;
 
 void fmm_options_default(fmm_options *opt);

@@ -43,6 +43,7 @@ struct Ctl {
     int bin_n[2][4];               // march-list sizes per work bin, by restart parity
     unsigned long long pops, march_calls, exchange_calls, tile_loads;
     unsigned long long rpops[2];   // pops of the current restart, by parity
+    unsigned long long rmin[2];    // bits of the smallest value popped in the restart (traces)
     unsigned long long feat[2][10];// band-size bins (8), sum of block mean speed (2^20 fixed
                                    // point), unused; by parity of the list being built
     long long restarts;
@@ -123,6 +124,13 @@ struct Lds {
     static constexpr size_t rhs_off = (tag_off + Geo<B>::TAGB + 15) / 16 * 16;
     static constexpr size_t scr_off = rhs_off + (Geo<B>::RHS_LDS ? sizeof(R) * T : 0);
     static constexpr size_t bytes = scr_off + 16 * 8 + 64;
+    // Waves per SIMD that the LDS footprint allows (160 KB per CU, 4 SIMDs).  For
+    // one wave per block the register budget is capped to match, up to 4 waves
+    // (128 registers): below that the march would spill.
+    static constexpr int wgs_per_cu = (int)(163840 / (bytes + 128));
+    static constexpr int lds_waves_per_simd = (wgs_per_cu * W + 3) / 4;
+    static constexpr int waves_per_simd =
+        W == 1 ? (lds_waves_per_simd > 4 ? 4 : (lds_waves_per_simd < 1 ? 1 : lds_waves_per_simd)) : 1;
 };
 
 // Copy NVEC 16-byte vectors global -> LDS (or back), eight per thread in flight
@@ -220,11 +228,22 @@ struct MinPick {
 };
 
 // Locate_Min over the band: the lexicographic (psi, tile index) minimum.
-// Each lane scans 8 consecutive slots per 16-byte read, keeping its
-// best (value, key) pair branch-free, key = index << 16 | slot.  psi >= 0, so
+// Each lane reads 8 consecutive slots per 16-byte read and reduces them with
+// two shallow trees: the minimum value first, then the smallest key among its
+// slots holding that value, key = index << 16 | slot.  psi >= 0 (+0 only), so
 // IEEE bit patterns order like the values; the cross-lane step takes the
 // minimum value first (high then low word for FP64), then the minimum key
 // among the lanes holding it.  Returns the same result in every lane.
+// Minimum of two band values.  FP32: on the bit patterns (one integer min; psi >= +0
+// and +inf order like their bits).  FP64: a compare and select.
+__device__ __forceinline__ float val_min(float a, float b)
+{
+    return __uint_as_float(min(__float_as_uint(a), __float_as_uint(b)));
+}
+__device__ __forceinline__ double val_min(double a, double b) { return b < a ? b : a; }
+__device__ __forceinline__ bool val_eq(float a, float b) { return __float_as_uint(a) == __float_as_uint(b); }
+__device__ __forceinline__ bool val_eq(double a, double b) { return a == b; }
+
 template <typename R, int W>
 __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band,
                                                   const uint16_t *g_band, int cap,
@@ -255,19 +274,24 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
         for (int j = 0; j < 8; ++j) {
             const uint32_t sl = (uint32_t)(base + j);
             const uint32_t id = (w4[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
-            ids[j] = sl < (uint32_t)n ? id : 0u;
+            ids[j] = sl < (uint32_t)n ? id : 0u;  // tile point 0 (a corner) is never used: +inf
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) vs[j] = s_psi[ids[j]];
+        // minimum value of the 8 slots (tree of depth 3)
+        const R m = val_min(val_min(val_min(vs[0], vs[1]), val_min(vs[2], vs[3])),
+                            val_min(val_min(vs[4], vs[5]), val_min(vs[6], vs[7])));
+        // smallest key among the slots holding it
+        uint32_t ks[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t sl = (uint32_t)(base + j);
-            const R v = sl < (uint32_t)n ? vs[j] : inf;
-            const uint32_t key = (ids[j] << 16) | sl;
-            const bool better = (v < bv) | ((v == bv) & (key < bk));
-            bv = better ? v : bv;
-            bk = better ? key : bk;
-        }
+        for (int j = 0; j < 8; ++j)
+            ks[j] = val_eq(vs[j], m) ? ((ids[j] << 16) | (uint32_t)(base + j)) : ~0u;
+        const uint32_t k0 = min(min(ks[0], ks[1]), min(ks[2], ks[3]));
+        const uint32_t k1 = min(min(ks[4], ks[5]), min(ks[6], ks[7]));
+        const uint32_t km = min(k0, k1);
+        const bool better = (m < bv) | (val_eq(m, bv) & (km < bk));
+        bv = better ? m : bv;
+        bk = better ? km : bk;
     }
     const uint32_t vh = KeyBits<R>::hi(bv);
     const uint32_t mh = wave_min_u32(vh);

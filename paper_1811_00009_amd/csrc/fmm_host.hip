@@ -274,6 +274,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     std::memset(&hc, 0, sizeof(hc));
     hc.n_list[1] = (int)first.size();  // restart 1 marches list[1] (all in bin 0)
     hc.bin_n[1][0] = (int)first.size();
+    hc.rmin[0] = hc.rmin[1] = ~0ull;
 
     HIPCHK(hipMemcpyAsync(ws.prob.p, descs.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ws.src.p, ents.data(), sizeof(SrcEntry) * ents.size(), hipMemcpyHostToDevice, st));

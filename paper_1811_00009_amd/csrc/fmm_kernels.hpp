@@ -18,6 +18,7 @@ struct TraceRow {
     int64_t t_end;
     int32_t active;
     int32_t next_active;
+    double min_popped;
 };
 
 constexpr double kLogMinMult = -1.3862943611198906;  // ln(1/4)
@@ -424,6 +425,12 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
             continue;
         }
         ++loads;
+        if (kp.trace && tid == 0) {  // the block accepts its band minimum first
+            const double v = (double)bm;
+            unsigned long long vb;
+            __builtin_memcpy(&vb, &v, sizeof(v));
+            atomicMin(&ctl->rmin[c], vb);
+        }
         march_block<R, B, W>(kp, ib, pd, bound, smem, pops);
     }
     if (tid == 0 && mcalls) {
@@ -553,7 +560,8 @@ __device__ void restart_features(const Ctl *ctl, int cn, int n_next, int64_t nbl
 // per restart (after the marching step, after the exchanging step).  The bound
 // lives in registers, identical in every work-group.
 template <typename R, int B, int W>
-__global__ void __launch_bounds__(64 * W) k_persistent(KParams<R> kp)
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(Lds<R, B, W>::waves_per_simd))) k_persistent(KParams<R> kp)
 {
     extern __shared__ __align__(16) char smem[];
     const int G = (int)gridDim.x, w = (int)blockIdx.x, tid = threadIdx.x;
@@ -572,6 +580,7 @@ __global__ void __launch_bounds__(64 * W) k_persistent(KParams<R> kp)
             ctl->n_list[c ^ 1] = 0;
             ctl->q_head[c ^ 1] = 0;
             ctl->rpops[c ^ 1] = 0;
+            ctl->rmin[c ^ 1] = ~0ull;
             for (int k = 0; k < 4; ++k) ctl->bin_n[c ^ 1][k] = 0;
             for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
             t0 = wall_ticks();
@@ -598,6 +607,10 @@ __global__ void __launch_bounds__(64 * W) k_persistent(KParams<R> kp)
             row->t_end = wall_ticks();
             row->active = ctl->n_list[c];
             row->next_active = nnext;
+            const unsigned long long mb = ctl->rmin[c];
+            double mv = INFINITY;
+            if (mb != ~0ull) __builtin_memcpy(&mv, &mb, sizeof(mv));
+            row->min_popped = mv;
         }
         if (nnext == 0) {
             if (w == 0 && tid == 0) {
@@ -637,12 +650,14 @@ __global__ void k_restart_prologue(KParams<R> kp, int64_t r)
     ctl->n_list[c ^ 1] = 0;
     ctl->q_head[c ^ 1] = 0;
     ctl->rpops[c ^ 1] = 0;
+    ctl->rmin[c ^ 1] = ~0ull;
     for (int k = 0; k < 4; ++k) ctl->bin_n[c ^ 1][k] = 0;
     for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
 }
 
 template <typename R, int B, int W>
-__global__ void __launch_bounds__(64 * W) k_march(KParams<R> kp, int64_t r)
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(Lds<R, B, W>::waves_per_simd))) k_march(KParams<R> kp, int64_t r)
 {
     extern __shared__ __align__(16) char smem[];
     if (read_abort(kp.ctl)) return;

@@ -68,7 +68,7 @@ class Tuning(C.Structure):
 class TraceRow(C.Structure):
     _fields_ = [("feat", C.c_float * NFEAT), ("bound", C.c_double), ("stride_used", C.c_double),
                 ("pops", C.c_int64), ("t_start", C.c_int64), ("t_end", C.c_int64),
-                ("active", C.c_int32), ("next_active", C.c_int32)]
+                ("active", C.c_int32), ("next_active", C.c_int32), ("min_popped", C.c_double)]
 
 
 TRACE_ROW_BYTES = C.sizeof(TraceRow)
@@ -314,7 +314,8 @@ def trace_rows(trace_tensor, count: int):
         tr = TraceRow.from_buffer_copy(raw[r * TRACE_ROW_BYTES:(r + 1) * TRACE_ROW_BYTES])
         rows.append({"feat": np.array(tr.feat[:], dtype=np.float32), "bound": tr.bound,
                      "stride_used": tr.stride_used, "pops": tr.pops, "t_start": tr.t_start,
-                     "t_end": tr.t_end, "active": tr.active, "next_active": tr.next_active})
+                     "t_end": tr.t_end, "active": tr.active, "next_active": tr.next_active,
+                     "min_popped": tr.min_popped})
     return rows
 
 

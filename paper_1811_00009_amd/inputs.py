@@ -111,14 +111,22 @@ def coarse_cells(n: int = 1024, cells: int = 64, seed=(3,), dtype=np.float32,
 BATCH_SIDES = tuple(range(32, 193, 16))  # 32, 48, ..., 192
 
 
+def fourier_modes(rng, modes: int = 8):
+    """Draw the random modes (k_m, a_m, phi_m) of the Fourier speed, in draw order."""
+    out = []
+    for _ in range(modes):
+        kv = rng.integers(1, 5, size=3)            # wavenumbers 1..4 per axis
+        a = float(rng.uniform(-1.0, 1.0))
+        phi = float(rng.uniform(0.0, 2 * np.pi))
+        out.append((kv, a, phi))
+    return out
+
+
 def fourier_speed(n: int, rng, modes: int = 8, amp: float = 0.75, dtype=np.float32):
     """F = 1 + amp * g / max|g|, g(x) = sum_m a_m cos(2 pi k_m . x + phi_m)."""
     x, _ = _coords(n)
     g = np.zeros((n, n, n), dtype=np.float64)
-    for _ in range(modes):
-        kv = rng.integers(1, 5, size=3)            # wavenumbers 1..4 per axis
-        a = rng.uniform(-1.0, 1.0)
-        phi = rng.uniform(0.0, 2 * np.pi)
+    for kv, a, phi in fourier_modes(rng, modes):
         ph = (2 * np.pi * kv[2] * x[:, None, None] + 2 * np.pi * kv[1] * x[None, :, None]
               + 2 * np.pi * kv[0] * x[None, None, :])
         g += a * np.cos(ph + phi)
@@ -132,6 +140,45 @@ def batched_problem(s: int, dtype=np.float32) -> Problem:
     h = 1.0 / (n - 1)
     src = tuple(int(v) for v in rng.integers(1, n - 1, size=3))
     F = fourier_speed(n, rng, dtype=dtype)
+    return Problem(f"batched[{s}]", F, h, [(src[0], src[1], src[2], 0.0)], block=16,
+                   stride=2 * h, meta={"n": n, "seed": [4, s]})
+
+
+# ------------------------------------------------------------------ the same fields built on a GPU
+# Large workloads are evaluated on the device from the same random draws (FP64,
+# then cast), which keeps multi-GiB host arrays out of the benchmark.  The values
+# agree with the host versions to the last bit of the cast in all but rare cases
+# (device and host cosines may differ in the last FP64 bit).
+def expand_cells_device(V: np.ndarray, n: int, torch, dtype=None):
+    """Device tensor F[k, j, i] = V[k // r, j // r, i // r], r = n / cells."""
+    dtype = dtype or torch.float32
+    c = V.shape[0]
+    r = n // c
+    assert r * c == n
+    Vd = torch.from_numpy(np.ascontiguousarray(V)).to("cuda").to(dtype)
+    return Vd[:, None, :, None, :, None].expand(c, r, c, r, c, r).reshape(n, n, n).contiguous()
+
+
+def fourier_speed_device(n: int, modes, torch, amp: float = 0.75, dtype=None):
+    dtype = dtype or torch.float32
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * (1.0 / (n - 1))
+    g = torch.zeros((n, n, n), dtype=torch.float64, device="cuda")
+    for kv, a, phi in modes:
+        ph = (2 * math.pi * float(kv[2]) * x[:, None, None]
+              + 2 * math.pi * float(kv[1]) * x[None, :, None]
+              + 2 * math.pi * float(kv[0]) * x[None, None, :])
+        g += a * torch.cos(ph + phi)
+    g /= g.abs().max()
+    return (1.0 + amp * g).to(dtype).contiguous()
+
+
+def batched_problem_device(s: int, torch) -> Problem:
+    """batched_problem(s) with F built on the GPU (FP32)."""
+    rng = np.random.default_rng(np.random.SeedSequence([4, s]))
+    n = int(rng.choice(BATCH_SIDES))
+    h = 1.0 / (n - 1)
+    src = tuple(int(v) for v in rng.integers(1, n - 1, size=3))
+    F = fourier_speed_device(n, fourier_modes(rng), torch)
     return Problem(f"batched[{s}]", F, h, [(src[0], src[1], src[2], 0.0)], block=16,
                    stride=2 * h, meta={"n": n, "seed": [4, s]})
 
@@ -154,6 +201,29 @@ def stride_field(seed_words, n: int, cells: int = 64, dtype=np.float32,
     F = expand_cells(V, n, dtype) if materialize else None
     return Problem(f"stride_field{list(seed_words)}", F, h, [(src[0], src[1], src[2], 0.0)],
                    block=16, stride=2 * h, meta={"n": n, "cells": cells, "V": V})
+
+
+def fourier_field_device(seed_words, n: int, torch) -> Problem:
+    """Stride-network family: Fourier speed as in the batched workload, on an n^3 grid."""
+    rng = np.random.default_rng(np.random.SeedSequence(list(seed_words)))
+    src = tuple(int(v) for v in rng.integers(1, n - 1, size=3))
+    F = fourier_speed_device(n, fourier_modes(rng), torch)
+    return Problem(f"fourier{list(seed_words)}", F, 1.0 / (n - 1),
+                   [(src[0], src[1], src[2], 0.0)], block=16, meta={"n": n})
+
+
+def sine_field_device(seed_words, n: int, torch) -> Problem:
+    """Stride-network family: F = 1 + a sin(2 pi k x) sin(2 pi k y) sin(2 pi k z),
+    a ~ U[0.2, 0.9], k uniform in {1, 2, 3}, random interior source."""
+    rng = np.random.default_rng(np.random.SeedSequence(list(seed_words)))
+    src = tuple(int(v) for v in rng.integers(1, n - 1, size=3))
+    a = float(rng.uniform(0.2, 0.9))
+    k = int(rng.integers(1, 4))
+    x = torch.arange(n, dtype=torch.float64, device="cuda") * (1.0 / (n - 1))
+    s = torch.sin(2 * math.pi * k * x)
+    F = 1.0 + a * s[:, None, None] * s[None, :, None] * s[None, None, :]
+    return Problem(f"sine{list(seed_words)}", F.to(torch.float32).contiguous(), 1.0 / (n - 1),
+                   [(src[0], src[1], src[2], 0.0)], block=16, meta={"n": n, "a": a, "k": k})
 
 
 # --------------------------------------------------------------------------- the paper's cases

@@ -10,9 +10,9 @@ schedules the restarts), so the network trades time, never accuracy.
 Data flow (all GPU work through the library's C ABI):
   1. trace plain solves with fixed multipliers m in MULTIPLIERS: every restart
      records its raw features, bound and device time;
-  2. label: per field and per bin of the bound fraction, m* = the multiplier
-     with the highest front progress rate (bound advance per device second);
-     every trace row of that bin gets the target ln m*;
+  2. label: per field, m* = the multiplier whose solve took the least device
+     time, the target ln m* of every trace row of that field (a per-slab rule,
+     the slab of values made final fastest, is kept for analysis);
   3. standardise the features (training-set mean and std) and fit the network
      with the library's forward / backward / Adam kernels (full batch);
   4. pack the parameters and the standardisation into the device blob that
@@ -67,32 +67,59 @@ def trace_solve(fmm, F, h, sources, block=16, stride0=None, multiplier=1.0, rows
     return psi, st, fmm.trace_rows(trace, n)
 
 
-def label_traces(traces_by_m: dict, nbins: int = 16):
-    """traces_by_m: {m: rows} for one field.  Returns (X, y): raw features of every
-    row and the target ln m* of its bound-fraction bin."""
-    fmax = max(max(r["feat"][0] for r in rows) for rows in traces_by_m.values() if rows)
-    edges = np.linspace(0.0, fmax * (1 + 1e-9), nbins + 1)
-    rate = {m: np.zeros(nbins) for m in traces_by_m}
-    for m, rows in traces_by_m.items():
-        adv = np.zeros(nbins)
-        tim = np.zeros(nbins)
-        prev = 0.0
-        for r in rows:
-            b = int(np.clip(np.searchsorted(edges, r["feat"][0], side="right") - 1, 0, nbins - 1))
-            adv[b] += r["bound"] - prev
-            tim[b] += max(r["t_end"] - r["t_start"], 1) / TICKS_PER_S
-            prev = r["bound"]
-        rate[m] = np.where(tim > 0, adv / np.maximum(tim, 1e-12), 0.0)
-    ms = sorted(traces_by_m)
-    best = np.array([ms[int(np.argmax([rate[m][b] for m in ms]))] for b in range(nbins)])
+def finality_times(rows, edges):
+    """Device seconds from the start of the solve until no later restart accepts a value at
+    or below each edge: the time at which the solution below the edge is final (later
+    restarts of the block method can still correct values below the current bound)."""
+    t0 = rows[0]["t_start"]
+    T = np.zeros(len(edges))
+    for r in rows:
+        mp = r.get("min_popped", math.inf)
+        if math.isfinite(mp):
+            T = np.where(edges >= mp, np.maximum(T, (r["t_end"] - t0) / TICKS_PER_S), T)
+    return T
+
+
+def solve_seconds(rows):
+    """Device seconds of a traced solve (first restart start to last restart end)."""
+    return (rows[-1]["t_end"] - rows[0]["t_start"]) / TICKS_PER_S
+
+
+def label_traces(traces_by_m: dict, rule: str = "field", nbins: int = 12, window: int = 1):
+    """traces_by_m: {m: rows} for one field.  Returns (X, y): the raw features of every
+    restart that chose a next stride, and the target ln m*.
+
+    rule "field": m* is the multiplier whose whole solve took the least device time (every
+    restart of the field gets it).  rule "slab": the values [0, top] are cut into nbins
+    slabs (top = the largest value any restart accepted first); the cost of m on slab k is
+    the time its solve took to make slabs k-window .. k+window final (finality_times), and
+    the restarts whose bound lies in slab k get the cheapest m."""
+    ms = sorted(m for m, rows in traces_by_m.items() if rows)
+    if rule == "field":
+        best_m = min(ms, key=lambda m: solve_seconds(traces_by_m[m]))
+        label = lambda r: best_m  # noqa: E731
+    elif rule == "slab":
+        tops = [r.get("min_popped", math.inf) for m in ms for r in traces_by_m[m]]
+        top = max(v for v in tops if math.isfinite(v))
+        edges = np.linspace(0.0, top * (1 + 1e-9), nbins + 1)
+        fin = {m: finality_times(traces_by_m[m], edges) for m in ms}
+        best = []
+        for k in range(nbins):
+            lo, hi = max(k - window, 0), min(k + window + 1, nbins)
+            best.append(ms[int(np.argmin([fin[m][hi] - fin[m][lo] for m in ms]))])
+
+        def label(r):
+            b = int(np.clip(np.searchsorted(edges, r["bound"], side="right") - 1, 0, nbins - 1))
+            return best[b]
+    else:
+        raise ValueError(rule)
     X, y = [], []
-    for m, rows in traces_by_m.items():
-        for r in rows:
+    for m in ms:
+        for r in traces_by_m[m]:
             if r["next_active"] == 0:
                 continue  # the last restart has no next stride to choose
-            b = int(np.clip(np.searchsorted(edges, r["feat"][0], side="right") - 1, 0, nbins - 1))
             X.append(r["feat"])
-            y.append(math.log(best[b]))
+            y.append(math.log(label(r)))
     return np.array(X, dtype=np.float32).reshape(-1, NFEAT), np.array(y, dtype=np.float32)
 
 

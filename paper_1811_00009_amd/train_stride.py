@@ -1,0 +1,182 @@
+"""Train and evaluate the restart-stride network on the GPU.
+
+    python -m paper_1811_00009_amd.train_stride --fields 150 --out paper_1811_00009_amd/weights
+
+1. Traces: for each training field, one traced solve per fixed multiplier m in
+   stride.MULTIPLIERS (stride m * 2h); every restart records its features,
+   bound and device time.  Fields: coarse-cell speeds (64^3 cells, seeds (5, s),
+   n^3 grid) and, for variety, Fourier speeds (seeds (6, s)) and smooth sine
+   speeds (seeds (7, s)).
+2. Labels per field: the multiplier whose whole solve took the least device time
+   (stride.label_traces).
+3. Full-batch training with the library's forward / backward / Adam kernels.
+4. Held-out evaluation on coarse-cell fields with seeds (50, s) at eval_n^3, and
+   on a few unseen fields of the other families at n^3: device time of every
+   fixed multiplier and of the learned stride, and psi of the learned solve
+   against the fixed 2h solve (FP32 bar).
+
+Writes <out>/stride_mlp_b<B>.f32 (the device blob: 1505 parameters, 12 feature
+means, 12 feature standard deviations, little-endian FP32) and
+<out>/stride_mlp_b<B>.json (data, training and evaluation record).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def log(msg):
+    print(f"[train_stride] {msg}", flush=True)
+
+
+def field(seed_words, n, torch):
+    """(problem, device speed) of a stride-network field; the family is seed_words[0]:
+    5 / 50 coarse cells, 6 Fourier, 7 sine."""
+    from . import inputs
+    if seed_words[0] in (5, 50):
+        p = inputs.stride_field(seed_words, n, materialize=False)
+        return p, inputs.expand_cells_device(p.meta["V"], n, torch)
+    if seed_words[0] == 6:
+        p = inputs.fourier_field_device(seed_words, n, torch)
+    else:
+        p = inputs.sine_field_device(seed_words, n, torch)
+    return p, p.F
+
+
+def collect(fmm, stride, torch, plan, n, block, rule):
+    """plan: [(family seed word, count)]."""
+    Xs, ys, best, t0, k = [], [], [], time.perf_counter(), 0
+    for fam, count in plan:
+        for s in range(count):
+            p, F = field([fam, s], n, torch)
+            traces = {}
+            for m in stride.MULTIPLIERS:
+                _, st, rows = stride.trace_solve(fmm, F, p.h, p.sources, block=block,
+                                                 multiplier=m)
+                traces[m] = rows
+            X, y = stride.label_traces(traces, rule=rule)
+            Xs.append(X)
+            ys.append(y)
+            secs = {m: round(stride.solve_seconds(traces[m]) * 1e3, 1) for m in traces}
+            best.append((fam, s, min(secs, key=secs.get)))
+            if k % 5 == 0:
+                log(f"field {fam}/{s}: {len(y)} samples, ms per m {secs}, "
+                    f"{time.perf_counter() - t0:.0f} s")
+            k += 1
+            del F
+    return np.concatenate(Xs), np.concatenate(ys), best
+
+
+def evaluate(fmm, stride, torch, blob_dev, seeds, n, block):
+    """Device time of every fixed multiplier and of the learned stride on the held-out
+    fields `seeds` (seed words); psi of the learned solve against the fixed 2h solve."""
+    res = []
+    for sw in seeds:
+        p, F = field(sw, n, torch)
+        out = torch.empty_like(F)
+        row = {"seed": list(sw), "source": list(p.sources[0][:3]), "fixed_ms": {}}
+        fmm.solve(F, p.h, p.sources, block=block, out=out)  # warm-up
+        for m in stride.MULTIPLIERS:
+            _, st = fmm.solve(F, p.h, p.sources, block=block, stride=m * 2 * p.h, out=out,
+                              with_stats=True)
+            row["fixed_ms"][str(m)] = st["elapsed_ms"]
+            if m == 1.0:
+                ref = out.clone()
+        _, st = fmm.solve(F, p.h, p.sources, block=block, stride=2 * p.h, out=out,
+                          with_stats=True, stride_mode="learned", mlp_weights=blob_dev)
+        row["learned_ms"] = st["elapsed_ms"]
+        row["learned_restarts"] = st["restarts"]
+        row["learned_pops"] = st["pops"]
+        row["learned_final_bound"] = st["final_bound"]
+        d = float((out - ref).abs().max())
+        row["max_abs_diff_learned_vs_fixed_2h"] = d
+        row["within_fp32_bar_vs_fixed"] = d <= 1e-5 * float(ref.max())
+        res.append(row)
+        log(f"eval field {sw} at {n}^3: fixed {row['fixed_ms']} learned "
+            f"{row['learned_ms']:.1f} ms")
+        del F, out, ref
+    tot = {m: sum(r["fixed_ms"][str(m)] for r in res) for m in stride.MULTIPLIERS}
+    best_m = min(tot, key=tot.get)
+    learned = sum(r["learned_ms"] for r in res)
+    pts = len(res) * n ** 3
+    return {"n": n, "fields": res, "total_ms_fixed": {str(m): tot[m] for m in tot},
+            "best_fixed_multiplier": best_m, "total_ms_learned": learned,
+            "speedup_vs_fixed_2h": tot[1.0] / learned,
+            "speedup_vs_best_fixed": tot[best_m] / learned,
+            "Mpts_per_s_learned": pts / (learned / 1e3) / 1e6,
+            "Mpts_per_s_fixed_2h": pts / (tot[1.0] / 1e3) / 1e6,
+            "Mpts_per_s_best_fixed": pts / (tot[best_m] / 1e3) / 1e6}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--fields", type=int, default=60, help="coarse-cell training fields")
+    ap.add_argument("--fourier-fields", type=int, default=30)
+    ap.add_argument("--sine-fields", type=int, default=30)
+    ap.add_argument("--rule", default="field", choices=("field", "slab"))
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--block", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--eval-fields", type=int, default=8)
+    ap.add_argument("--eval-n", type=int, default=512)
+    ap.add_argument("--other-eval-fields", type=int, default=2)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  "weights"))
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import fmm, stride
+    fmm.load()
+    if not torch.cuda.is_available():
+        raise SystemExit("train_stride needs a GPU")
+    t0 = time.perf_counter()
+    plan = [(5, args.fields), (6, args.fourier_fields), (7, args.sine_fields)]
+    X, y, best = collect(fmm, stride, torch, plan, args.n, args.block, args.rule)
+    hist = {}
+    for fam, _, m in best:
+        hist.setdefault(fam, {}).setdefault(m, 0)
+        hist[fam][m] += 1
+    log(f"{len(y)} samples in {time.perf_counter() - t0:.0f} s; fastest multiplier per "
+        f"family {hist}")
+    blob, params, lh = stride.train(fmm, X, y, steps=args.steps, lr=args.lr)
+    log(f"loss {lh[0]:.4f} -> {lh[-1]:.4f} after {args.steps} steps")
+    os.makedirs(args.out, exist_ok=True)
+    path = os.path.join(args.out, f"stride_mlp_b{args.block}.f32")
+    blob.astype("<f4").tofile(path)
+    blob_dev = torch.from_numpy(blob.astype(np.float32)).cuda()
+    evals = {"coarse_cells_held_out": evaluate(
+        fmm, stride, torch, blob_dev, [[50, s] for s in range(args.eval_fields)], args.eval_n,
+        args.block)}
+    # unseen fields of the other families (seeds beyond the training range)
+    for name, fam in (("fourier_unseen", 6), ("sine_unseen", 7)):
+        evals[name] = evaluate(fmm, stride, torch, blob_dev,
+                               [[fam, 1000 + s] for s in range(args.other_eval_fields)],
+                               args.n, args.block)
+    for name, ev in evals.items():
+        log(f"{name}: learned {ev['Mpts_per_s_learned']:.1f} Mpts/s, fixed 2h "
+            f"{ev['Mpts_per_s_fixed_2h']:.1f}, best fixed (m={ev['best_fixed_multiplier']}) "
+            f"{ev['Mpts_per_s_best_fixed']:.1f}")
+    rec = {"blob": os.path.basename(path), "layout": "1505 params (W1 32x12, b1, W2 32x32, b2, "
+           "W3 1x32, b3), 12 feature means, 12 feature stds; FP32 little-endian",
+           "train": {"fields": {"coarse_cells (5, s)": args.fields,
+                                "fourier (6, s)": args.fourier_fields,
+                                "sine (7, s)": args.sine_fields},
+                     "n": args.n, "rule": args.rule, "fastest_multiplier_per_family": hist,
+                     "block": args.block, "multipliers": list(stride.MULTIPLIERS),
+                     "samples": int(len(y)), "steps": args.steps, "lr": args.lr,
+                     "loss_first": float(lh[0]), "loss_last": float(lh[-1])},
+           "eval": evals}
+    with open(os.path.join(args.out, f"stride_mlp_b{args.block}.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    log(f"wrote {path}")
+
+
+if __name__ == "__main__":
+    main()

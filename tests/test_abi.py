@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_sizes_match_header_layout():
     assert C.sizeof(fmm.Source) == 32
-    assert C.sizeof(fmm.TraceRow) == 48 + 8 * 5 + 8
+    assert C.sizeof(fmm.TraceRow) == 48 + 8 * 5 + 8 + 8
     assert C.sizeof(fmm.Stats) == 5 * 8 + 3 * 8 + 4 * 4
     assert C.sizeof(fmm.Options) == 64
 

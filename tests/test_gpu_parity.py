@@ -233,3 +233,28 @@ def test_band_beyond_lds_capacity_spills_exactly(fmm_lib, dtype):
     ref = oracle.block_fmm(wide.F, wide.h, wide.sources, block=16, stride=8 * wide.h, dtype=dtype)
     got, _ = _run(fmm_lib, wide, dtype, block=16, stride=8 * wide.h, band_lds_cap=512)
     assert np.array_equal(got, ref)
+
+
+# ------------------------------------------------------------------ the paper's test cases
+@pytest.mark.parametrize("case", [1, 2, 3, 4])
+def test_paper_cases_fp64(fmm_lib, case):
+    """The four point-source problems of Sec. 3.1 (cell-centred unit cube, source at the
+    centre; case 4 with F = 0 barriers) at 128^3: FP64 parity with the single-heap
+    baseline for 8^3 and 16^3 blocks and several strides, bitwise equality with the block
+    reference, and restart counts that fall as the stride grows (Sec. 3.4)."""
+    p = inputs.paper_case(case, 128)
+    base = oracle.fmm(p.F, p.h, p.sources)
+    restarts = []
+    for block, sh in ((8, 0.5), (16, 2.0), (16, 3.5), (16, math.inf)):
+        stride = sh * p.h
+        got, st = _run(fmm_lib, p, np.float64, block=block, stride=stride)
+        _assert_fp_parity(got, base, np.float64)
+        if block == 16:
+            restarts.append(st["restarts"])
+        if sh == 2.0:
+            ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=16, stride=stride, stats=True)
+            assert np.array_equal(got, ref)
+            assert st["pops"] == rs["pops"]
+    assert restarts[0] > restarts[1] > restarts[2]
+    if case == 4:
+        assert np.isinf(base).any()  # points inside the barriers stay unreached

@@ -126,10 +126,56 @@ def test_trace_rows_are_consistent(fmm_lib):
     psi, st, rows = stride_mod.trace_solve(fmm_lib, F, p.h, p.sources, block=8)
     assert len(rows) == st["restarts"]
     assert sum(r["pops"] for r in rows) == st["pops"]
+    assert rows[0]["min_popped"] == 0.0  # the source is accepted first
     for r_i, r in enumerate(rows):
         assert r["bound"] == pytest.approx((r_i + 1) * 2 * p.h)
+        if r["pops"] > 0:
+            assert r["min_popped"] <= r["bound"]
+        else:
+            assert math.isinf(r["min_popped"])
         assert r["t_end"] >= r["t_start"]
         if r["next_active"] > 0:
             assert sum(r["feat"][2:10]) == pytest.approx(1.0, abs=1e-5)
             assert 0.25 <= r["feat"][11] <= 2.0
     assert rows[-1]["next_active"] == 0
+
+
+def _trained_blob():
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(stride_mod.__file__), "weights", "stride_mlp_b16.f32")
+    blob = np.fromfile(path, dtype="<f4")
+    assert blob.size == 1505 + 24 and np.all(np.isfinite(blob))
+    return torch.from_numpy(blob).cuda()
+
+
+def test_trained_network_keeps_psi_and_beats_fixed_2h(fmm_lib):
+    """The committed network on an unseen coarse-cell field (the training family, 256^3):
+    psi stays within the FP32 bar of the fixed-stride solve and of the single-heap oracle
+    (on a box around the source), and the solve is faster than the plain 2h stride."""
+    import torch
+    from boxcut import box_origin, box_slices, exact_region
+    blob = _trained_blob()
+    n = 256
+    p = inputs.stride_field([50, 100], n, materialize=False)
+    F = inputs.expand_cells_device(p.meta["V"], n, torch)
+    fixed_ms, learned_ms = [], []
+    for _ in range(3):
+        fixed, sf = fmm_lib.solve(F, p.h, p.sources, block=16, with_stats=True)
+        fixed_ms.append(sf["elapsed_ms"])
+        learned, sl = fmm_lib.solve(F, p.h, p.sources, block=16, with_stats=True,
+                                    stride_mode="learned", mlp_weights=blob)
+        learned_ms.append(sl["elapsed_ms"])
+    tol = 1e-5 * float(fixed.max())
+    assert float((learned - fixed).abs().max()) <= tol
+    si, sj, sk = p.sources[0][:3]
+    lo = box_origin((si, sj, sk), (n, n, n), 96)
+    sl_ = box_slices(lo, 96)
+    ref = oracle.fmm(np.ascontiguousarray(F[sl_].cpu().numpy()), p.h,
+                     [(si - lo[0], sj - lo[1], sk - lo[2], 0.0)], dtype=np.float32)
+    keep = exact_region(ref, lo, (n, n, n))
+    got = learned[sl_].cpu().numpy()
+    assert np.max(np.abs(got[keep].astype(np.float64) - ref[keep])) <= 1e-5 * ref[keep].max()
+    # the gain: fewer device milliseconds than the method with its default stride
+    assert min(learned_ms) < min(fixed_ms), (learned_ms, fixed_ms)
+    assert sl["restarts"] != sf["restarts"]  # the network did choose other strides

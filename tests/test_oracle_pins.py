@@ -368,21 +368,48 @@ def test_adam_step_matches_closed_form_first_step():
 
 # ----------------------------------------------------------------------- stride labels (host logic)
 def test_stride_labels_pick_fastest_multiplier_per_bin():
+    """Label rule: the multiplier that makes a slab of values final first wins the slab; a
+    stride that defers corrections (small values accepted again later) pays for them."""
     from paper_1811_00009_amd import stride as stride_mod
 
-    def rows(m, rate):
-        out, b = [], 0.0
-        for k in range(20):
+    def rows(m, secs_per_restart, late_fix_at=None):
+        out, b, t = [], 0.0, 0
+        n = int(round(1.0 / (0.01 * m)))
+        for k in range(n):
+            lo = b
             b += 0.01 * m
+            t += int(secs_per_restart * 1e8)
             out.append({"feat": np.array([b] + [0.0] * 11, np.float32), "bound": b,
-                        "t_start": 0, "t_end": int(0.01 * m / rate * 1e8),
-                        "next_active": 1 if k < 19 else 0})
+                        "t_start": 0 if k == 0 else out[-1]["t_end"], "t_end": t,
+                        "min_popped": lo, "next_active": 1})
+        if late_fix_at is not None:  # a correction below late_fix_at after the bound passed
+            t += int(secs_per_restart * 1e8)
+            out.append({"feat": np.array([b] + [0.0] * 11, np.float32), "bound": b + 0.01 * m,
+                        "t_start": out[-1]["t_end"], "t_end": t, "min_popped": late_fix_at,
+                        "next_active": 1})
+        out[-1]["next_active"] = 0
         return out
-    traces = {0.5: rows(0.5, 1.0), 2.0: rows(2.0, 3.0), 8.0: rows(8.0, 2.0)}
-    X, y = stride_mod.label_traces(traces, nbins=4)
-    assert X.shape[1] == 12 and len(X) == len(y) == 57
-    # 2.0 has the highest progress rate wherever it has data
-    assert np.all(np.isclose(np.exp(y[X[:, 0] <= 0.4]), 2.0))
+
+    # m=0.5: 200 restarts of 1 ms; m=2: 50 restarts of 3 ms (faster per unit of bound), but
+    # m=2 accepts a value of 0.1 again at its very end, so the slab holding 0.1, (0.0995,
+    # 0.199], is final only after 0.153 s: that slab goes to m=0.5, every other slab to m=2
+    traces = {0.5: rows(0.5, 0.001), 2.0: rows(2.0, 0.003, late_fix_at=0.1)}
+    X, y = stride_mod.label_traces(traces, rule="slab", nbins=10, window=0)
+    assert X.shape[1] == 12 and len(X) == len(y) == 199 + 50
+    lab = np.exp(y)
+    bound = X[:, 0]
+    assert np.allclose(lab[(bound > 0.105) & (bound < 0.195)], 0.5, rtol=1e-6)
+    assert np.allclose(lab[bound < 0.095], 2.0, rtol=1e-6)
+    assert np.allclose(lab[(bound > 0.205) & (bound < 0.99)], 2.0, rtol=1e-6)
+    fin = stride_mod.finality_times(traces[2.0], np.array([0.05, 0.5]))
+    assert fin[0] == pytest.approx(0.009) and fin[1] == pytest.approx(0.153)
+    # whole-field rule: m=0.5 takes 0.200 s, m=2 takes 0.153 s -> every row gets ln 2
+    assert stride_mod.solve_seconds(traces[0.5]) == pytest.approx(0.2)
+    Xf, yf = stride_mod.label_traces(traces, rule="field")
+    assert len(Xf) == 249 and np.allclose(np.exp(yf), 2.0)
+    traces[2.0] = rows(2.0, 0.0045, late_fix_at=0.1)  # now 0.2295 s: m=0.5 wins
+    Xf, yf = stride_mod.label_traces(traces, rule="field")
+    assert np.allclose(np.exp(yf), 0.5)
     blob = stride_mod.pack_blob(stride_mod.init_params(0), np.zeros(12), np.ones(12))
     assert blob.shape == (1505 + 24,) and blob.dtype == np.float32
 
