@@ -302,7 +302,14 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
         ml = wave_min_u32(tie ? vl : ~0u);
         tie = tie && (vl == ml);
     }
-    uint32_t mk = wave_min_u32(tie ? bk : ~0u);
+    // the key among the lanes holding the minimum: usually one lane does (read its key);
+    // equal values in several lanes take the cross-lane minimum
+    const uint64_t tm = ballot(tie);
+    uint32_t mk;
+    if (__builtin_popcountll(tm) == 1)
+        mk = (uint32_t)__builtin_amdgcn_readlane((int)bk, (int)__builtin_ctzll(tm));
+    else
+        mk = wave_min_u32(tie ? bk : ~0u);
     uint32_t h = mh, l = ml;
     if constexpr (W > 1) {
         __shared__ uint32_t s[16];
@@ -344,13 +351,25 @@ template <typename R>
 __device__ __forceinline__ R axis_candidate(R psq, R lo, bool klo, R hi, bool khi)
 {
     const R inf = (R)INFINITY;
-    int d = 0;
-    if (klo && psq > lo) d = -1;
-    if (khi && psq > hi) {
-        if (d == 0 || hi < lo) d = 1;
-    }
-    return d < 0 ? lo : (d > 0 ? hi : inf);
+    const R a = klo ? lo : inf, b = khi ? hi : inf;
+    const R c = fmin(a, b);  // equal values: either side gives the same candidate
+    return c < psq ? c : inf;
 }
+
+// The largest value of type R that is <= the double bound: "v > bound" in double equals
+// "v > below_or_equal<R>(bound)" in R for every v of type R (bound >= 0).
+__device__ __forceinline__ float below_or_equal_f(double bound)
+{
+    float f = (float)bound;
+    if ((double)f > bound) f = __uint_as_float(__float_as_uint(f) - 1u);  // f > 0 here
+    return f;
+}
+template <typename R>
+__device__ __forceinline__ R bound_in(double bound);
+template <>
+__device__ __forceinline__ float bound_in<float>(double bound) { return below_or_equal_f(bound); }
+template <>
+__device__ __forceinline__ double bound_in<double>(double bound) { return bound; }
 
 __device__ __forceinline__ float root2(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double root2(double x) { return __builtin_sqrt(x); }

@@ -133,33 +133,48 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     copy_band<NT>(reinterpret_cast<FMM_LDS v4u *>(s_band), reinterpret_cast<const v4u *>(g_band),
                   n < cap ? n : cap, tid);
     FMM_LDS R *s_rhs = reinterpret_cast<FMM_LDS R *>(lds + L::rhs_off);
-    if constexpr (Gm::RHS_LDS)
+    if constexpr (Gm::RHS_LDS) {
         copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_rhs),
                                                    reinterpret_cast<const v4u *>(g_rhs), tid);
+    } else {
+        // h^2/F^2 stays in device memory: touch each of its cache lines once now, so the
+        // solves of the march hit in cache instead of each paying a memory round trip
+        constexpr int LINE = 128 / (int)sizeof(R);
+        R acc = (R)0;
+#pragma unroll
+        for (int k = 0; k < (T + LINE * NT - 1) / (LINE * NT); ++k) {
+            const int l = tid + k * NT;
+            acc += g_rhs[l * LINE < T ? l * LINE : T - 1];
+        }
+        asm volatile("" ::"v"(acc));  // keeps the loads (the ghost slots of the tile are unset)
+    }
     __syncthreads();
 
     // per-lane neighbour direction of Update_Neighbors: lanes 0-5 = -x, +x, -y, +y, -z, +z
     const int dI = (lane == 1) - (lane == 0), dJ = (lane == 3) - (lane == 2),
               dK = (lane == 5) - (lane == 4);
     const int dOff = dI + P * (dJ + P * dK);
-    uint32_t dirty = 0;
+    uint32_t fb_acc = 0;  // faces of Upsilon touched by this lane's updates
     bool active = true;
     R exit_min = inf;
-    long long npops = 0;
+    int npops = 0;
+    const int pop_cap = __builtin_amdgcn_readfirstlane((int)kp.pop_cap);
+    const R rbound = bound_in<R>(bound);  // psi > rbound  <=>  (double)psi > bound
     for (;;) {
+        n = __builtin_amdgcn_readfirstlane(n);  // wave-uniform: scalar branches below
         if (n == 0) {  // empty heap: deactivate
             active = false;
             exit_min = inf;
             break;
         }
         const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n);
-        if ((double)mp.v > bound) {  // beyond the restart bound: stop (deactivate past width)
+        if (mp.v > rbound) {  // beyond the restart bound: stop (deactivate past width)
             if ((double)mp.v > pd.width) active = false;
             exit_min = mp.v;
             break;
         }
         const int p = mp.idx;
-        if (++npops > kp.pop_cap) {
+        if (++npops > pop_cap) {
             raise_error(kp.ctl, kErrPopCap);
             exit_min = mp.v;
             break;
@@ -180,15 +195,24 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             }
             const uint8_t tq = s_tag[q];  // lane 6 reads the accepted point's own tag
             const R psq = s_psi[q];
-            uint16_t last;
-            if (n < cap) last = s_band[n];
-            else last = __builtin_nontemporal_load(g_band + n);
+            // Remove_Min: lane 7 moves the band's last slot into the hole.  The branch on
+            // the wave-uniform n < cap keeps the usual all-LDS case free of any wait on
+            // device memory (the h^2/F^2 load above stays in flight until the solve).
+            if (n < cap) {
+                const uint16_t last = (uint16_t)__builtin_amdgcn_readfirstlane(s_band[n]);
+                if (lane == 7) s_band[mp.slot] = last;  // mp.slot <= n < cap
+            } else {
+                // every lane reads the same slot; taking it as a wave-uniform value also
+                // completes the load inside this branch
+                const uint16_t last =
+                    (uint16_t)__builtin_amdgcn_readfirstlane(__builtin_nontemporal_load(g_band + n));
+                if (lane == 7) {
+                    if (mp.slot < cap) s_band[mp.slot] = last;
+                    else __builtin_nontemporal_store(last, g_band + mp.slot);
+                }
+            }
             if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
                 s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
-            if (lane == 7) {
-                if (mp.slot < cap) s_band[mp.slot] = last;
-                else __builtin_nontemporal_store(last, g_band + mp.slot);
-            }
             bool ins = false;
             uint32_t fb = 0;
             if (inb && (tq & kStatus) != kKnownFix && psq > mp.v) {
@@ -197,8 +221,10 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 for (int ax = 0; ax < 3; ++ax) {
                     const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
                     const R lo = s_psi[q - off], hi = s_psi[q + off];
-                    const bool klo = is_known(s_tag[q - off]) || (q - off == p);
-                    const bool khi = is_known(s_tag[q + off]) || (q + off == p);
+                    // p itself reads as known: lane 6 wrote its tag above, and one
+                    // wave's LDS accesses complete in program order
+                    const bool klo = is_known(s_tag[q - off]);
+                    const bool khi = is_known(s_tag[q + off]);
                     c[ax] = axis_candidate<R>(psq, lo, klo, hi, khi);
                 }
                 const R t = quad_root<R>(c[0], c[1], c[2], rhs);
@@ -224,8 +250,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-#pragma unroll
-            for (int k = 0; k < 6; ++k) dirty |= (uint32_t)__builtin_amdgcn_readlane((int)fb, k);
+            fb_acc |= fb;
             if constexpr (W > 1) {
                 if (lane == 0) s_bc[0] = n;
             }
@@ -241,6 +266,9 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         }
     }
 
+    uint32_t dirty = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) dirty |= (uint32_t)__builtin_amdgcn_readlane((int)fb_acc, k);
     // LDS -> tile
     copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<v4u *>(g_psi),
                                                reinterpret_cast<const FMM_LDS v4u *>(s_psi), tid);
