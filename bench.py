@@ -192,8 +192,11 @@ def run_single(args, torch, fmm):
 
     stats, wall = timed(step, args.steps, args.warmup, "fixed")
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        # known traffic for counter calibration: fill 1 GiB, then copy 1 GiB into a second
+        # buffer (the copy reads 2^30 bytes and writes 2^30 bytes)
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
+        torch.cuda.synchronize()
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
