@@ -124,13 +124,16 @@ struct Lds {
     static constexpr size_t rhs_off = (tag_off + Geo<B>::TAGB + 15) / 16 * 16;
     static constexpr size_t scr_off = rhs_off + (Geo<B>::RHS_LDS ? sizeof(R) * T : 0);
     static constexpr size_t bytes = scr_off + 16 * 8 + 64;
-    // Waves per SIMD that the LDS footprint allows (160 KB per CU, 4 SIMDs).  For
-    // one wave per block the register budget is capped to match, up to 4 waves
-    // (128 registers): below that the march would spill.
+    // Waves per SIMD that the LDS footprint allows (160 KB per CU, 4 SIMDs).  The
+    // register budget of the march kernels is capped to match, up to 4 waves (128
+    // registers) for one FP32 wave per block and 3 waves (168 registers) otherwise:
+    // below that the march would spill.
     static constexpr int wgs_per_cu = (int)(163840 / (bytes + 128));
     static constexpr int lds_waves_per_simd = (wgs_per_cu * W + 3) / 4;
+    static constexpr int max_waves = (W == 1 && sizeof(R) == 4) ? 4 : 3;
     static constexpr int waves_per_simd =
-        W == 1 ? (lds_waves_per_simd > 4 ? 4 : (lds_waves_per_simd < 1 ? 1 : lds_waves_per_simd)) : 1;
+        lds_waves_per_simd > max_waves ? max_waves
+                                       : (lds_waves_per_simd < 1 ? 1 : lds_waves_per_simd);
 };
 
 // Copy NVEC 16-byte vectors global -> LDS (or back), eight per thread in flight
