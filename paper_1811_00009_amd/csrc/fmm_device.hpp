@@ -41,6 +41,8 @@ struct Ctl {
     int n_list[2];                 // march-list sizes, by restart parity
     int q_head[2];                 // march work-queue heads, by restart parity
     int bin_n[2][4];               // march-list sizes per work bin, by restart parity
+    int x_n[2];                    // exchange-list sizes, by restart parity
+    int x_head[2];                 // exchange work-queue heads, by restart parity
     unsigned long long pops, march_calls, exchange_calls, tile_loads;
     unsigned long long rpops[2];   // pops of the current restart, by parity
     unsigned long long rmin[2];    // bits of the smallest value popped in the restart (traces)
@@ -51,7 +53,7 @@ struct Ctl {
 };
 
 // Device-side error codes (stored in Ctl::abort; mapped to fmm.h codes by the host).
-constexpr int kErrPopCap = 1, kErrTimeout = 2, kErrRestarts = 3, kErrBadSpeed = 4;
+constexpr int kErrPopCap = 1, kErrTimeout = 2, kErrRestarts = 3, kErrBadSpeed = 4, kErrList = 5;
 
 // Per-problem descriptor (a batch holds several).
 struct ProbDesc {
@@ -77,6 +79,7 @@ struct KParams {
     float *fmean;          // [nblk] mean speed of the block's interior
     int32_t *lastpops;     // [nblk] pops of the block's last march (work estimate)
     int32_t *list0, *list1;// march lists, by restart parity; 4 bins of nblk entries each
+    int32_t *xlist;        // [nblk] blocks whose C flags went up in this restart
     Ctl *ctl;
     const ProbDesc *prob;
     int32_t nprob;

@@ -71,7 +71,7 @@ int ensure(DevBuf &b, size_t bytes, const char *what)
 
 // Library-owned device memory of one GPU, grown on demand and kept for reuse.
 struct Workspace {
-    DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, lastpops, list0, list1, ctl, prob,
+    DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, lastpops, list0, list1, xlist, ctl, prob,
         src, plastr, ppops;
     hipEvent_t e0 = nullptr, e1 = nullptr, l0 = nullptr, l1 = nullptr;
 };
@@ -198,6 +198,7 @@ int map_device_error(int code)
     case kErrPopCap: return fail(FMM_ENOCONV, "device watchdog: a march call exceeded the pop cap");
     case kErrTimeout: return fail(FMM_ENOCONV, "device watchdog: a grid barrier wait timed out");
     case kErrRestarts: return fail(FMM_ENOCONV, "restart cap reached");
+    case kErrList: return fail(FMM_EHIP, "internal error: a work list overflowed or held a bad block index");
     default: return fail(FMM_EHIP, "unknown device error " + std::to_string(code));
     }
 }
@@ -250,6 +251,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
         (rc = ensure(ws.lastpops, (size_t)nblk * 4, "block work estimates")) ||
         (rc = ensure(ws.list0, (size_t)nblk * 4 * 4, "march list 0")) ||
         (rc = ensure(ws.list1, (size_t)nblk * 4 * 4, "march list 1")) ||
+        (rc = ensure(ws.xlist, (size_t)nblk * 4, "exchange list")) ||
         (rc = ensure(ws.ctl, sizeof(Ctl), "control block")) ||
         (rc = ensure(ws.prob, sizeof(ProbDesc) * nprob, "problem table")) ||
         (rc = ensure(ws.plastr, sizeof(int32_t) * nprob, "problem restarts")) ||
@@ -297,6 +299,7 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     kp.lastpops = (int32_t *)ws.lastpops.p;
     kp.list0 = (int32_t *)ws.list0.p;
     kp.list1 = (int32_t *)ws.list1.p;
+    kp.xlist = (int32_t *)ws.xlist.p;
     kp.ctl = (Ctl *)ws.ctl.p;
     kp.prob = (const ProbDesc *)ws.prob.p;
     kp.nprob = nprob;

@@ -105,7 +105,8 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
 // h^2/F^2 load of every neighbour issued ahead of both.
 template <typename R, int B, int W>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
-                            char *smem, unsigned long long &pops_acc)
+                            int c, char *smem, unsigned long long &pops_acc, bool &a_out,
+                            int &n_out, int &pops_out)
 {
     using L = Lds<R, B, W>;
     using Gm = Geo<B>;
@@ -293,9 +294,17 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         bz += (f == 5) - (f == 4);
         if (bx >= 0 && by >= 0 && bz >= 0 && bx < pd.mx && by < pd.my && bz < pd.mz) {
             const int64_t nb = pd.blk0 + bx + (int64_t)pd.mx * (by + (int64_t)pd.my * bz);
-            atomicOr(&kp.Cm[nb], 1u << (f ^ 1));
+            // the first flag raised on nb in this restart puts nb on the exchange list
+            if (atomicOr(&kp.Cm[nb], 1u << (f ^ 1)) == 0u) {
+                const int pos = atomicAdd(&kp.ctl->x_n[c], 1);
+                if (pos < kp.nblk) kp.xlist[pos] = (int32_t)nb;
+                else raise_error(kp.ctl, kErrList);  // cannot happen: one entry per block
+            }
         }
     }
+    a_out = active;
+    n_out = n;
+    pops_out = npops;
     pops_acc += (unsigned long long)npops;
     if (kp.nprob > 1 && tid == 0) atomicAdd(&kp.prob_pops[kp.blk_prob[ib]], (unsigned long long)npops);
     __syncthreads();  // LDS is reused by the next block
@@ -315,7 +324,6 @@ template <typename R, int B, int W>
 __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, const ProbDesc &pd,
                                char *smem, bool &a_out, int &n_out)
 {
-    using L = Lds<R, B, W>;
     constexpr int P = Geo<B>::P, T = Geo<B>::T, NT = 64 * W, FB = B * B, BAND = Geo<B>::BAND,
                   TAGB = Geo<B>::TAGB;
     const int tid = threadIdx.x;
@@ -401,17 +409,45 @@ __device__ void exchange_block(const KParams<R> &kp, int64_t ib, uint32_t cm, co
 }
 
 // ---------------------------------------------------------------- phase drivers
+// Band-size bin of the restart features (see fmm.h).
+__device__ __forceinline__ int band_bin(int nb)
+{
+    return nb >= 4096 ? 7 : nb >= 1024 ? 6 : nb >= 256 ? 5 : nb >= 64 ? 4 : nb >= 16 ? 3
+           : nb >= 4 ? 2 : nb >= 1 ? 1 : 0;
+}
+
+// Put active block ib on the march list of the next restart, list[(r + 1) & 1], in
+// one of 4 bins by its expected work est (longest first), and add it to the restart
+// features.  One thread per block.
+template <typename R>
+__device__ void append_next(const KParams<R> &kp, int c, int64_t r, int64_t ib, int est, int nb)
+{
+    Ctl *ctl = kp.ctl;
+    int32_t *next = c ? kp.list0 : kp.list1;
+    const int k = est >= 768 ? 0 : (est >= 256 ? 1 : (est >= 64 ? 2 : 3));
+    const int pos = atomicAdd(&ctl->bin_n[c ^ 1][k], 1);
+    if (pos < kp.nblk) next[(int64_t)k * kp.nblk + pos] = (int32_t)ib;
+    else raise_error(ctl, kErrList);  // cannot happen: one entry per block
+    atomicAdd(&ctl->n_list[c ^ 1], 1);
+    if (kp.want_features) {
+        atomicAdd(&ctl->feat[c ^ 1][band_bin(nb)], 1ull);
+        atomicAdd(&ctl->feat[c ^ 1][8], (unsigned long long)((double)kp.fmean[ib] * kFixScale + 0.5));
+    }
+    if (kp.nprob > 1) atomicMax(&kp.prob_lastr[kp.blk_prob[ib]], (int)r);
+}
+
 // Marching step of restart r: blocks of the march list list[r & 1] are taken
 // from a work queue, longest expected march first: the list is binned when it
-// is built by the pops of each block's previous march (blocks without one go
-// first), a cheap longest-job-first order that shortens the wait for the
-// slowest block at the barrier.  A block whose exact band minimum is above its bound is
-// not loaded: Alg. 4 would stop at once without changing anything (only the
-// width test can flip its activation).
+// is built by each block's expected work (the pops of its previous march or its
+// band size, whichever is larger), a cheap longest-job-first order that shortens
+// the wait for the slowest block at the barrier.  A block whose exact band
+// minimum is above its bound is not loaded: Alg. 4 would stop at once without
+// changing anything (only the width test can flip its activation).  A block
+// that stays active goes on the next march list right away (an exchange can
+// only activate a block, never deactivate it).
 template <typename R, int B, int W>
 __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem)
 {
-    using L = Lds<R, B, W>;
     const int c = (int)(r & 1);
     const int tid = threadIdx.x;
     Ctl *ctl = kp.ctl;
@@ -429,7 +465,7 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         const int item = s_item[0];
         __syncthreads();
         if (item >= ncur) break;
-        // bins in order: the blocks with the largest bands (the longest marches) first
+        // bins in order: the blocks with the most expected work first
         int k = 0, off = item;
         if (off >= bn0) {
             off -= bn0;
@@ -443,13 +479,27 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
                 }
             }
         }
+        if (off >= kp.nblk) {  // counts out of step with the list: stop, never read past it
+            if (tid == 0) raise_error(ctl, kErrList);
+            break;
+        }
         const int64_t ib = cur[(int64_t)k * kp.nblk + off];
+        if ((uint64_t)ib >= (uint64_t)kp.nblk) {
+            if (tid == 0) raise_error(ctl, kErrList);
+            break;
+        }
         const ProbDesc pd = kp.nprob == 1 ? kp.prob[0] : kp.prob[kp.blk_prob[ib]];
         const double bound = kp.stride_mode ? lbound : fixed_bound(r, pd.stride, pd.width);
         ++mcalls;
         const R bm = kp.bmin[ib];
         if ((double)bm > bound) {
-            if ((double)bm > pd.width && tid == 0) kp.A[ib] = 0;
+            if (tid == 0) {
+                if ((double)bm > pd.width) kp.A[ib] = 0;
+                else {
+                    const int nb = kp.band_n[ib];
+                    append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nb), nb);
+                }
+            }
             continue;
         }
         ++loads;
@@ -459,7 +509,10 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
             __builtin_memcpy(&vb, &v, sizeof(v));
             atomicMin(&ctl->rmin[c], vb);
         }
-        march_block<R, B, W>(kp, ib, pd, bound, smem, pops);
+        bool a;
+        int nb, np;
+        march_block<R, B, W>(kp, ib, pd, bound, c, smem, pops, a, nb, np);
+        if (tid == 0 && a) append_next<R>(kp, c, r, ib, max(np, nb), nb);
     }
     if (tid == 0 && mcalls) {
         atomicAdd(&ctl->pops, pops);
@@ -469,77 +522,45 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
     }
 }
 
-// Exchanging step of restart r, fused with the compaction of the next march
-// list.  Work-group w owns blocks w, w + G, w + 2G, ...; it scans their C flags
-// 64 at a time (ballot), runs Alg. 5 on every flagged one, and appends its
-// blocks whose activation is set to list[(r + 1) & 1] (ballot, in-wave prefix
-// count, one atomic per wave).  The activation of an owned block is final once
-// its own exchange is done, so no extra barrier is needed before compaction.
+// Exchanging step of restart r: the blocks whose C flags were raised in this
+// restart's marching step (the exchange list, built as the flags went up) are
+// taken from a work queue and run Alg. 5.  A block that the exchange activates
+// joins the next march list; for a block that was already on it the band-size
+// feature moves to the bin of its new band size.
 template <typename R, int B, int W>
 __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int G, int w)
 {
     const int c = (int)(r & 1);
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x;
     Ctl *ctl = kp.ctl;
-    int32_t *next = c ? kp.list0 : kp.list1;
+    const int nx = __hip_atomic_load(&ctl->x_n[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ int s_item[1];
     unsigned long long xcalls = 0;
-    for (int64_t base = 0; (int64_t)w + (int64_t)G * base < kp.nblk; base += 64) {
-        const int64_t ib = (int64_t)w + (int64_t)G * (base + lane);
-        const bool valid = ib < kp.nblk;
-        const uint32_t cm = valid ? kp.Cm[ib] : 0u;
-        bool a = valid ? (kp.A[ib] != 0) : false;
-        int nb = valid ? kp.band_n[ib] : 0;
-        const int lp = valid ? kp.lastpops[ib] : 0;
-        uint64_t em = ballot(cm != 0u);
-        while (em) {
-            const int l = __ffsll((long long)em) - 1;
-            em &= em - 1;
-            const int64_t ibl = (int64_t)w + (int64_t)G * (base + l);
-            const uint32_t cml = (uint32_t)__builtin_amdgcn_readlane((int)cm, l);
-            const ProbDesc pd = kp.nprob == 1 ? kp.prob[0] : kp.prob[kp.blk_prob[ibl]];
-            bool an;
-            int nn;
-            exchange_block<R, B, W>(kp, ibl, cml, pd, smem, an, nn);
-            ++xcalls;
-            if (lane == l) {
-                a = an;
-                nb = nn;
-            }
+    for (;;) {
+        if (tid == 0) s_item[0] = atomicAdd(&ctl->x_head[c], 1);
+        __syncthreads();
+        const int item = s_item[0];
+        __syncthreads();
+        if (item >= nx) break;
+        const int64_t ib = item < kp.nblk ? kp.xlist[item] : -1;
+        if ((uint64_t)ib >= (uint64_t)kp.nblk) {
+            if (tid == 0) raise_error(ctl, kErrList);
+            break;
         }
-        if (wid == 0) {
-            const uint64_t am = ballot(a);
-            if (am) {
-                if (lane == 0) atomicAdd(&ctl->n_list[c ^ 1], (int)__popcll(am));
-                const int wbin = lp >= 768 ? 0 : (lp >= 256 ? 1 : (lp >= 64 ? 2 : 3));
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uint64_t mk = ballot(a && wbin == k);
-                    if (!mk) continue;
-                    int pos0 = 0;
-                    if (lane == 0) pos0 = atomicAdd(&ctl->bin_n[c ^ 1][k], (int)__popcll(mk));
-                    pos0 = __builtin_amdgcn_readfirstlane(pos0);
-                    if (a && wbin == k)
-                        next[(int64_t)k * kp.nblk + pos0 + (int)lanes_below(mk)] = (int32_t)ib;
-                }
-                if (kp.want_features) {
-                    int bin = 0;
-                    if (nb >= 1) bin = 1;
-                    if (nb >= 4) bin = 2;
-                    if (nb >= 16) bin = 3;
-                    if (nb >= 64) bin = 4;
-                    if (nb >= 256) bin = 5;
-                    if (nb >= 1024) bin = 6;
-                    if (nb >= 4096) bin = 7;
-                    for (int k = 0; k < 8; ++k) {
-                        const int cnt = (int)__popcll(ballot(a && bin == k));
-                        if (lane == 0 && cnt) atomicAdd(&ctl->feat[c ^ 1][k], (unsigned long long)cnt);
-                    }
-                    unsigned long long fx =
-                        a ? (unsigned long long)((double)kp.fmean[ib] * kFixScale + 0.5) : 0ull;
-                    for (int o = 32; o >= 1; o >>= 1) fx += __shfl_xor(fx, o);
-                    if (lane == 0) atomicAdd(&ctl->feat[c ^ 1][8], fx);
-                }
-                if (kp.nprob > 1 && a) atomicMax(&kp.prob_lastr[kp.blk_prob[ib]], (int)r);
+        const uint32_t cm = kp.Cm[ib];
+        const bool a0 = kp.A[ib] != 0;
+        const int n0 = kp.band_n[ib];
+        const ProbDesc pd = kp.nprob == 1 ? kp.prob[0] : kp.prob[kp.blk_prob[ib]];
+        bool an;
+        int nn;
+        exchange_block<R, B, W>(kp, ib, cm, pd, smem, an, nn);
+        ++xcalls;
+        if (tid == 0) {
+            if (an && !a0) {
+                append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nn), nn);
+            } else if (a0 && kp.want_features && band_bin(nn) != band_bin(n0)) {
+                atomicAdd(&ctl->feat[c ^ 1][band_bin(n0)], ~0ull);  // -1
+                atomicAdd(&ctl->feat[c ^ 1][band_bin(nn)], 1ull);
             }
         }
     }
@@ -604,18 +625,29 @@ __global__ void __launch_bounds__(64 * W)
             if (lbound > p0.width) lbound = p0.width;
         }
         int64_t t0 = 0;
+        // Counters of the next restart's queues.  The next march list, list[c ^ 1], is
+        // appended to from this restart's marching step on, so its size, bins and
+        // features were cleared after the marching step of the previous restart (below).
         if (w == 0 && tid == 0) {
-            ctl->n_list[c ^ 1] = 0;
             ctl->q_head[c ^ 1] = 0;
             ctl->rpops[c ^ 1] = 0;
             ctl->rmin[c ^ 1] = ~0ull;
-            for (int k = 0; k < 4; ++k) ctl->bin_n[c ^ 1][k] = 0;
-            for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
+            ctl->x_n[c ^ 1] = 0;
+            ctl->x_head[c ^ 1] = 0;
             t0 = wall_ticks();
         }
+        const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
         march_phase<R, B, W>(kp, r, lbound, smem);
         grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
         if (read_abort(ctl)) break;
+        // list[c] has been consumed: clear its counters for restart r + 1, which appends
+        // to it (nothing reads or appends to them again before the next barrier)
+        if (w == 0 && tid == 0) {
+            ctl->n_list[c] = 0;
+            for (int k = 0; k < 4; ++k) ctl->bin_n[c][k] = 0;
+            for (int k = 0; k < 10; ++k) ctl->feat[c][k] = 0;
+        }
         exchange_phase<R, B, W>(kp, r, smem, G, w);
         grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
         if (read_abort(ctl)) break;
@@ -633,7 +665,7 @@ __global__ void __launch_bounds__(64 * W)
             row->pops = (int64_t)ctl->rpops[c];
             row->t_start = t0;
             row->t_end = wall_ticks();
-            row->active = ctl->n_list[c];
+            row->active = ncur;
             row->next_active = nnext;
             const unsigned long long mb = ctl->rmin[c];
             double mv = INFINITY;
@@ -679,6 +711,8 @@ __global__ void k_restart_prologue(KParams<R> kp, int64_t r)
     ctl->q_head[c ^ 1] = 0;
     ctl->rpops[c ^ 1] = 0;
     ctl->rmin[c ^ 1] = ~0ull;
+    ctl->x_n[c ^ 1] = 0;
+    ctl->x_head[c ^ 1] = 0;
     for (int k = 0; k < 4; ++k) ctl->bin_n[c ^ 1][k] = 0;
     for (int k = 0; k < 10; ++k) ctl->feat[c ^ 1][k] = 0;
 }
