@@ -86,7 +86,7 @@ def cpu_baseline(p, workload, seconds_target=15.0):
     import oracle
     from paper_1811_00009_amd import inputs
     n = p.F.shape[0] if p.F is not None else p.meta["n"]
-    side = min(n, 256)
+    side = min(n, 320)  # ~15 s of one host core
     src = p.sources[0]
     lo = [min(max(int(src[a]) - side // 2, 0), n - side) for a in range(3)]
     if workload == "coarse_cells_1024":

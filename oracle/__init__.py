@@ -188,3 +188,43 @@ def adam_step(params, grad, m, v, lr, beta1, beta2, eps, t):
     g = np.ascontiguousarray(grad, dtype=np.float64)
     _check(lib.orc_adam_step(_ptr(params), _ptr(g), _ptr(m), _ptr(v), len(params), lr, beta1,
                              beta2, eps, t), "orc_adam_step")
+
+
+# ------------------------------------------------------------------ parallel CPU baseline
+_par = None
+
+
+def _load_par():
+    global _par
+    if _par is not None:
+        return _par
+    path = os.path.join(_HERE, "libcpu_parallel.so")
+    if not os.path.exists(path):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(path)
+    f = lib.cpu_block_fmm_par_f64
+    f.restype = C.c_int
+    f.argtypes = [_i64, _i64, _i64, _dbl, _vp, _i32, _vp, _vp, _i32, _dbl, _dbl, _i32, _i64,
+                  _vp, _vp, _vp, _vp]
+    _par = lib
+    return lib
+
+
+def block_fmm_parallel(F: np.ndarray, h: float, sources, block: int, stride: float,
+                       width: float = math.inf, threads: int = 0, stats: bool = False):
+    """The paper's parallel CPU solver (Sec. 2.7): the block method of block_fmm with
+    each step's blocks spread over OpenMP threads; FP64.  A comparison baseline."""
+    lib = _load_par()
+    F = _speed(F, np.float64)
+    nz, ny, nx = F.shape
+    idx, val = _sources(F.shape, sources, np.float64)
+    psi = np.empty_like(F)
+    r, pops, used = _i64(0), _i64(0), _i32(0)
+    rc = lib.cpu_block_fmm_par_f64(nx, ny, nz, h, _ptr(F), len(idx), _ptr(idx), _ptr(val), block,
+                                   stride, width, threads, 0, _ptr(psi), C.byref(r), C.byref(pops),
+                                   C.byref(used))
+    _check(rc, "cpu_block_fmm_par_f64")
+    if stats:
+        return psi, {"restarts": r.value, "pops": pops.value, "threads": used.value}
+    return psi

@@ -324,28 +324,18 @@ static void FN(blk_free)(FN(blk_t) *b)
     free(b->hp.a);
 }
 
-int FN(orc_block_fmm)(int64_t nx, int64_t ny, int64_t nz, double h, const REAL *F, int32_t nsrc,
-                      const int64_t *src_idx, const REAL *src_val, int32_t B, double stride,
-                      double width, const double *bounds, int32_t nbounds, int32_t literal,
-                      int64_t max_restarts, REAL *psi, int64_t *restarts_out, int64_t *pops_out,
-                      int64_t *march_calls_out, int64_t *exchange_calls_out)
+/* Alg. 1 for every block: psi <- inf, G <- FAR, empty heap, A <- F; points of the
+   padded block (interior and ghost faces) that are sources become KNOWN_FIX, enter
+   the heap, and activate the block.  C <- F (Alg. 6).  blk holds nblk zeroed
+   entries; on error the caller frees what was allocated. */
+static int FN(blocks_init)(FN(blk_t) *blk, int64_t nx, int64_t ny, int32_t B, int64_t mx,
+                           int64_t my, int64_t mz, int32_t nsrc, const int64_t *src_idx,
+                           const REAL *src_val)
 {
-    if (nx <= 0 || ny <= 0 || nz <= 0 || !(h > 0) || nsrc <= 0 || B <= 0) return ORC_EINVAL;
-    if (nx % B || ny % B || nz % B || !(stride > 0)) return ORC_EINVAL;
-    const int64_t N = nx * ny * nz;
-    for (int32_t s = 0; s < nsrc; ++s)
-        if (src_idx[s] < 0 || src_idx[s] >= N || !(src_val[s] >= 0)) return ORC_EINVAL;
-    const int64_t mx = nx / B, my = ny / B, mz = nz / B, nblk = mx * my * mz;
+    const int64_t nblk = mx * my * mz;
     const int P = B + 2;
     const int64_t T = (int64_t)P * P * P;
-    const REAL hr = (REAL)h;
     int rc = 0;
-    FN(blk_t) *blk = (FN(blk_t) *)calloc((size_t)nblk, sizeof(FN(blk_t)));
-    if (!blk) return ORC_ENOMEM;
-
-    /* Alg. 1 for every block: psi <- inf, G <- FAR, empty heap, A <- F; points of the
-       padded block (interior and ghost faces) that are sources become KNOWN_FIX,
-       enter the heap, and activate the block.  C <- F (Alg. 6). */
     for (int64_t ib = 0; ib < nblk; ++ib) {
         FN(blk_t) *b = &blk[ib];
         b->bx = ib % mx;
@@ -358,7 +348,7 @@ int FN(orc_block_fmm)(int64_t nx, int64_t ny, int64_t nz, double h, const REAL *
         b->Y = (int32_t *)malloc((size_t)T * sizeof(int32_t));
         if (!b->psi || !b->G || !b->pos || !b->inY || !b->Y) {
             rc = ORC_ENOMEM;
-            goto done;
+            return rc;
         }
         for (int64_t t = 0; t < T; ++t) {
             b->psi[t] = (REAL)INFINITY;
@@ -389,13 +379,172 @@ int FN(orc_block_fmm)(int64_t nx, int64_t ny, int64_t nz, double h, const REAL *
                     int64_t t = li + P * (lj + P * lk);
                     if (src_val[s] < b->psi[t]) b->psi[t] = src_val[s];
                     b->G[t] = ORC_KNOWN_FIX;
-                    if ((rc = FN(heap_push_or_up)(&b->hp, t)) != 0) goto done;
+                    if ((rc = FN(heap_push_or_up)(&b->hp, t)) != 0) return rc;
                     b->A = 1;
                 }
     }
 
-    int64_t r = 0, pops = 0, march_calls = 0, exch_calls = 0;
+    return rc;
+}
+
+/* Interior of every block -> linear psi. */
+static void FN(blocks_gather)(const FN(blk_t) *blk, int64_t nx, int64_t ny, int32_t B, int64_t nblk,
+                              REAL *psi)
+{
+    const int P = B + 2;
+    for (int64_t ib = 0; ib < nblk; ++ib) {
+        const FN(blk_t) *b = &blk[ib];
+        for (int lk = 1; lk <= B; ++lk)
+            for (int lj = 1; lj <= B; ++lj)
+                for (int li = 1; li <= B; ++li) {
+                    int64_t g = (b->bx * B + li - 1) +
+                                nx * ((b->by * B + lj - 1) + ny * (b->bz * B + lk - 1));
+                    psi[g] = b->psi[li + (int64_t)P * (lj + (int64_t)P * lk)];
+                }
+    }
+}
+
+/* Alg. 4 (with Alg. 2 restricted to the block's interior) on block ib for one
+   restart bound, then C^nb <- TRUE for every neighbour nb whose ghosts meet
+   Upsilon^ib.  Touches only block ib, except the neighbours' C flags (written with
+   atomic stores, so that several blocks may march at once). */
+static int FN(march_one)(FN(blk_t) *blk, int64_t ib, int32_t B, int64_t mx, int64_t my, int64_t mz,
+                         int64_t nx, int64_t ny, REAL hr, const REAL *F, double bound,
+                         double width, int32_t literal, int64_t *pops)
+{
+    const int P = B + 2;
     const int64_t toff[6] = {-1, 1, -P, P, -(int64_t)P * P, (int64_t)P * P};
+    int rc = 0;
+    FN(blk_t) *b = &blk[ib];
+    for (int32_t y = 0; y < b->nY; ++y) b->inY[b->Y[y]] = 0;
+    b->nY = 0; /* Upsilon <- empty */
+    for (;;) {
+        if (b->hp.n == 0) {
+            b->A = 0;
+            break;
+        }
+        const int64_t p = b->hp.a[0];
+        if ((double)b->psi[p] > bound) {
+            if ((double)b->psi[p] > width) b->A = 0;
+            break;
+        }
+        if (b->G[p] != ORC_KNOWN_FIX) b->G[p] = ORC_KNOWN_NEW;
+        FN(heap_pop)(&b->hp);
+        ++*pops;
+        const int pi = (int)(p % P), pj = (int)((p / P) % P), pk = (int)(p / (P * P));
+        /* Alg. 2 restricted to Omega^ib (interior points of the block) */
+        for (int nb = 0; nb < 6; ++nb) {
+            int qi = pi, qj = pj, qk = pk;
+            switch (nb) {
+            case 0: qi--; break;
+            case 1: qi++; break;
+            case 2: qj--; break;
+            case 3: qj++; break;
+            case 4: qk--; break;
+            default: qk++; break;
+            }
+            if (qi < 1 || qi > B || qj < 1 || qj > B || qk < 1 || qk > B) continue;
+            const int64_t q = qi + (int64_t)P * (qj + (int64_t)P * qk);
+            if (b->G[q] == ORC_KNOWN_FIX || !(b->psi[q] > b->psi[p])) continue;
+            const int64_t gq = (b->bx * B + qi - 1) +
+                               nx * ((b->by * B + qj - 1) + ny * (b->bz * B + qk - 1));
+            if (F[gq] == 0) continue;
+            REAL nv[6];
+            int nk[6];
+            for (int d = 0; d < 6; ++d) {
+                nv[d] = b->psi[q + toff[d]];
+                nk[d] = (b->G[q + toff[d]] == ORC_KNOWN_FIX || b->G[q + toff[d]] == ORC_KNOWN_NEW);
+            }
+            REAL t = FN(solve_quadratic)(b->psi[q], nv, nk, FN(rhs_of)(hr, F[gq]), literal);
+            if (t < b->psi[q]) {
+                b->psi[q] = t;
+                b->G[q] = ORC_BAND;
+                if ((rc = FN(heap_push_or_up)(&b->hp, q)) != 0) return rc;
+                /* Pi^ib: the block's own points that are ghosts of a neighbour */
+                if ((qi == 1 || qi == B || qj == 1 || qj == B || qk == 1 || qk == B) && !b->inY[q]) {
+                    b->inY[q] = 1;
+                    b->Y[b->nY++] = (int32_t)q;
+                }
+            }
+        }
+    }
+    /* C^nb(ib) <- TRUE for every neighbour nb whose ghosts meet Upsilon^ib */
+    for (int32_t y = 0; y < b->nY; ++y) {
+        const int64_t q = b->Y[y];
+        const int qi = (int)(q % P), qj = (int)((q / P) % P), qk = (int)(q / (P * P));
+        const int onface[6] = {qi == 1, qi == B, qj == 1, qj == B, qk == 1, qk == B};
+        for (int f = 0; f < 6; ++f) {
+            if (!onface[f]) continue;
+            int64_t nbx = b->bx + (f == 1) - (f == 0);
+            int64_t nby = b->by + (f == 3) - (f == 2);
+            int64_t nbz = b->bz + (f == 5) - (f == 4);
+            if (nbx < 0 || nby < 0 || nbz < 0 || nbx >= mx || nby >= my || nbz >= mz) continue;
+            __atomic_store_n(&blk[nbx + mx * (nby + my * nbz)].C[f ^ 1], 1, __ATOMIC_RELAXED);
+        }
+    }
+    return 0;
+}
+
+/* Alg. 5 on block ib: for every flagged face, the points of the neighbour's
+   Upsilon that lie on ib's ghost layer are copied (value and category) when
+   smaller and enter ib's heap; then C^ib <- F and the block is activated when its
+   heap minimum is within width.  Writes only block ib; reads the neighbours'
+   interior points and Upsilon lists, which no exchange writes. */
+static int FN(exchange_one)(FN(blk_t) *blk, int64_t ib, int32_t B, int64_t mx, int64_t my,
+                            double width)
+{
+    const int P = B + 2;
+    int rc = 0;
+    FN(blk_t) *b = &blk[ib];
+    for (int f = 0; f < 6; ++f) {
+        if (!b->C[f]) continue;
+        int64_t nbx = b->bx + (f == 1) - (f == 0);
+        int64_t nby = b->by + (f == 3) - (f == 2);
+        int64_t nbz = b->bz + (f == 5) - (f == 4);
+        const FN(blk_t) *o = &blk[nbx + mx * (nby + my * nbz)];
+        /* points of Upsilon^nb that lie in the ghost layer Theta^ib on face f */
+        for (int32_t y = 0; y < o->nY; ++y) {
+            const int64_t q = o->Y[y];
+            int qi = (int)(q % P), qj = (int)((q / P) % P), qk = (int)(q / (P * P));
+            /* the neighbour's boundary layer facing ib is its face f^1 */
+            const int onface[6] = {qi == 1, qi == B, qj == 1, qj == B, qk == 1, qk == B};
+            if (!onface[f ^ 1]) continue;
+            /* the same grid point in ib's tile */
+            int gi = qi + (int)((nbx - b->bx) * B);
+            int gj = qj + (int)((nby - b->by) * B);
+            int gk = qk + (int)((nbz - b->bz) * B);
+            const int64_t g = gi + (int64_t)P * (gj + (int64_t)P * gk);
+            if (b->psi[g] > o->psi[q]) {
+                b->psi[g] = o->psi[q];
+                b->G[g] = o->G[q];
+                if ((rc = FN(heap_push_or_up)(&b->hp, g)) != 0) return rc;
+            }
+        }
+    }
+    for (int f = 0; f < 6; ++f) b->C[f] = 0;
+    if (b->hp.n > 0 && (double)b->psi[b->hp.a[0]] <= width) b->A = 1;
+    return 0;
+}
+
+int FN(orc_block_fmm)(int64_t nx, int64_t ny, int64_t nz, double h, const REAL *F, int32_t nsrc,
+                      const int64_t *src_idx, const REAL *src_val, int32_t B, double stride,
+                      double width, const double *bounds, int32_t nbounds, int32_t literal,
+                      int64_t max_restarts, REAL *psi, int64_t *restarts_out, int64_t *pops_out,
+                      int64_t *march_calls_out, int64_t *exchange_calls_out)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0 || !(h > 0) || nsrc <= 0 || B <= 0) return ORC_EINVAL;
+    if (nx % B || ny % B || nz % B || !(stride > 0)) return ORC_EINVAL;
+    const int64_t N = nx * ny * nz;
+    for (int32_t s = 0; s < nsrc; ++s)
+        if (src_idx[s] < 0 || src_idx[s] >= N || !(src_val[s] >= 0)) return ORC_EINVAL;
+    const int64_t mx = nx / B, my = ny / B, mz = nz / B, nblk = mx * my * mz;
+    const REAL hr = (REAL)h;
+    int rc = 0;
+    FN(blk_t) *blk = (FN(blk_t) *)calloc((size_t)nblk, sizeof(FN(blk_t)));
+    if (!blk) return ORC_ENOMEM;
+    if ((rc = FN(blocks_init)(blk, nx, ny, B, mx, my, mz, nsrc, src_idx, src_val)) != 0) goto done;
+
+    int64_t r = 0, pops = 0, march_calls = 0, exch_calls = 0;
     for (;;) {
         ++r;
         if (max_restarts > 0 && r > max_restarts) {
@@ -414,112 +563,19 @@ int FN(orc_block_fmm)(int64_t nx, int64_t ny, int64_t nz, double h, const REAL *
 
         /* marching step: Alg. 4 on every block with A = TRUE */
         for (int64_t ib = 0; ib < nblk; ++ib) {
-            FN(blk_t) *b = &blk[ib];
-            if (!b->A) continue;
+            if (!blk[ib].A) continue;
             ++march_calls;
-            for (int32_t y = 0; y < b->nY; ++y) b->inY[b->Y[y]] = 0;
-            b->nY = 0; /* Upsilon <- empty */
-            for (;;) {
-                if (b->hp.n == 0) {
-                    b->A = 0;
-                    break;
-                }
-                const int64_t p = b->hp.a[0];
-                if ((double)b->psi[p] > bound) {
-                    if ((double)b->psi[p] > width) b->A = 0;
-                    break;
-                }
-                if (b->G[p] != ORC_KNOWN_FIX) b->G[p] = ORC_KNOWN_NEW;
-                FN(heap_pop)(&b->hp);
-                ++pops;
-                const int pi = (int)(p % P), pj = (int)((p / P) % P), pk = (int)(p / (P * P));
-                /* Alg. 2 restricted to Omega^ib (interior points of the block) */
-                for (int nb = 0; nb < 6; ++nb) {
-                    int qi = pi, qj = pj, qk = pk;
-                    switch (nb) {
-                    case 0: qi--; break;
-                    case 1: qi++; break;
-                    case 2: qj--; break;
-                    case 3: qj++; break;
-                    case 4: qk--; break;
-                    default: qk++; break;
-                    }
-                    if (qi < 1 || qi > B || qj < 1 || qj > B || qk < 1 || qk > B) continue;
-                    const int64_t q = qi + (int64_t)P * (qj + (int64_t)P * qk);
-                    if (b->G[q] == ORC_KNOWN_FIX || !(b->psi[q] > b->psi[p])) continue;
-                    const int64_t gq = (b->bx * B + qi - 1) +
-                                       nx * ((b->by * B + qj - 1) + ny * (b->bz * B + qk - 1));
-                    if (F[gq] == 0) continue;
-                    REAL nv[6];
-                    int nk[6];
-                    for (int d = 0; d < 6; ++d) {
-                        nv[d] = b->psi[q + toff[d]];
-                        nk[d] = (b->G[q + toff[d]] == ORC_KNOWN_FIX ||
-                                 b->G[q + toff[d]] == ORC_KNOWN_NEW);
-                    }
-                    REAL t = FN(solve_quadratic)(b->psi[q], nv, nk, FN(rhs_of)(hr, F[gq]), literal);
-                    if (t < b->psi[q]) {
-                        b->psi[q] = t;
-                        b->G[q] = ORC_BAND;
-                        if ((rc = FN(heap_push_or_up)(&b->hp, q)) != 0) goto done;
-                        /* Pi^ib: the block's own points that are ghosts of a neighbour */
-                        if ((qi == 1 || qi == B || qj == 1 || qj == B || qk == 1 || qk == B) &&
-                            !b->inY[q]) {
-                            b->inY[q] = 1;
-                            b->Y[b->nY++] = (int32_t)q;
-                        }
-                    }
-                }
-            }
-            /* C^nb(ib) <- TRUE for every neighbour nb whose ghosts meet Upsilon^ib */
-            for (int32_t y = 0; y < b->nY; ++y) {
-                const int64_t q = b->Y[y];
-                const int qi = (int)(q % P), qj = (int)((q / P) % P), qk = (int)(q / (P * P));
-                const int onface[6] = {qi == 1, qi == B, qj == 1, qj == B, qk == 1, qk == B};
-                for (int f = 0; f < 6; ++f) {
-                    if (!onface[f]) continue;
-                    int64_t nbx = b->bx + (f == 1) - (f == 0);
-                    int64_t nby = b->by + (f == 3) - (f == 2);
-                    int64_t nbz = b->bz + (f == 5) - (f == 4);
-                    if (nbx < 0 || nby < 0 || nbz < 0 || nbx >= mx || nby >= my || nbz >= mz)
-                        continue;
-                    blk[nbx + mx * (nby + my * nbz)].C[f ^ 1] = 1;
-                }
-            }
+            if ((rc = FN(march_one)(blk, ib, B, mx, my, mz, nx, ny, hr, F, bound, width, literal,
+                                    &pops)) != 0)
+                goto done;
         }
 
         /* exchanging step: Alg. 5 on every block with any C = TRUE */
         for (int64_t ib = 0; ib < nblk; ++ib) {
-            FN(blk_t) *b = &blk[ib];
+            const FN(blk_t) *b = &blk[ib];
             if (!(b->C[0] | b->C[1] | b->C[2] | b->C[3] | b->C[4] | b->C[5])) continue;
             ++exch_calls;
-            for (int f = 0; f < 6; ++f) {
-                if (!b->C[f]) continue;
-                int64_t nbx = b->bx + (f == 1) - (f == 0);
-                int64_t nby = b->by + (f == 3) - (f == 2);
-                int64_t nbz = b->bz + (f == 5) - (f == 4);
-                FN(blk_t) *o = &blk[nbx + mx * (nby + my * nbz)];
-                /* points of Upsilon^nb that lie in the ghost layer Theta^ib on face f */
-                for (int32_t y = 0; y < o->nY; ++y) {
-                    const int64_t q = o->Y[y];
-                    int qi = (int)(q % P), qj = (int)((q / P) % P), qk = (int)(q / (P * P));
-                    /* the neighbour's boundary layer facing ib is its face f^1 */
-                    const int onface[6] = {qi == 1, qi == B, qj == 1, qj == B, qk == 1, qk == B};
-                    if (!onface[f ^ 1]) continue;
-                    /* the same grid point in ib's tile */
-                    int gi = qi + (int)((nbx - b->bx) * B);
-                    int gj = qj + (int)((nby - b->by) * B);
-                    int gk = qk + (int)((nbz - b->bz) * B);
-                    const int64_t g = gi + (int64_t)P * (gj + (int64_t)P * gk);
-                    if (b->psi[g] > o->psi[q]) {
-                        b->psi[g] = o->psi[q];
-                        b->G[g] = o->G[q];
-                        if ((rc = FN(heap_push_or_up)(&b->hp, g)) != 0) goto done;
-                    }
-                }
-            }
-            for (int f = 0; f < 6; ++f) b->C[f] = 0;
-            if (b->hp.n > 0 && (double)b->psi[b->hp.a[0]] <= width) b->A = 1;
+            if ((rc = FN(exchange_one)(blk, ib, B, mx, my, width)) != 0) goto done;
         }
 
         int any = 0;
@@ -527,18 +583,7 @@ int FN(orc_block_fmm)(int64_t nx, int64_t ny, int64_t nz, double h, const REAL *
         if (!any) break;
     }
 
-    if (rc == 0) {
-        for (int64_t ib = 0; ib < nblk; ++ib) {
-            FN(blk_t) *b = &blk[ib];
-            for (int lk = 1; lk <= B; ++lk)
-                for (int lj = 1; lj <= B; ++lj)
-                    for (int li = 1; li <= B; ++li) {
-                        int64_t g = (b->bx * B + li - 1) +
-                                    nx * ((b->by * B + lj - 1) + ny * (b->bz * B + lk - 1));
-                        psi[g] = b->psi[li + (int64_t)P * (lj + (int64_t)P * lk)];
-                    }
-        }
-    }
+    if (rc == 0) FN(blocks_gather)(blk, nx, ny, B, nblk, psi);
     if (restarts_out) *restarts_out = r;
     if (pops_out) *pops_out = pops;
     if (march_calls_out) *march_calls_out = march_calls;

@@ -1,12 +1,14 @@
 """Train and evaluate the restart-stride network on the GPU.
 
-    python -m paper_1811_00009_amd.train_stride --fields 150 --out paper_1811_00009_amd/weights
+    python -m paper_1811_00009_amd.train_stride --fields 60 --out paper_1811_00009_amd/weights
 
 1. Traces: for each training field, one traced solve per fixed multiplier m in
    stride.MULTIPLIERS (stride m * 2h); every restart records its features,
    bound and device time.  Fields: coarse-cell speeds (64^3 cells, seeds (5, s),
-   n^3 grid) and, for variety, Fourier speeds (seeds (6, s)) and smooth sine
-   speeds (seeds (7, s)).
+   n^3 grid); Fourier speeds (seeds (6, s)) and smooth sine speeds (seeds
+   (7, s)) can be mixed in (off by default: their fastest multipliers split
+   between ~1 and 4-8, and a regression on such labels lands in between, where
+   the solve is slowest).
 2. Labels per field: the multiplier whose whole solve took the least device time
    (stride.label_traces).
 3. Full-batch training with the library's forward / backward / Adam kernels.
@@ -117,8 +119,8 @@ def evaluate(fmm, stride, torch, blob_dev, seeds, n, block):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--fields", type=int, default=60, help="coarse-cell training fields")
-    ap.add_argument("--fourier-fields", type=int, default=30)
-    ap.add_argument("--sine-fields", type=int, default=30)
+    ap.add_argument("--fourier-fields", type=int, default=0)
+    ap.add_argument("--sine-fields", type=int, default=0)
     ap.add_argument("--rule", default="field", choices=("field", "slab"))
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block", type=int, default=16)

@@ -438,3 +438,18 @@ def test_box_restriction_is_exact_below_boundary_layer_minimum(seed):
         assert np.array_equal(ref[keep], full[box_slices(lo, box)][keep])
         # just past the region the restriction is no longer exact somewhere (the check is sharp)
         assert not np.array_equal(ref, full[box_slices(lo, box)])
+
+
+# ------------------------------------------------------------------ parallel CPU baseline
+@pytest.mark.parametrize("seed,block,stride_h,threads", [(70, 8, 2.0, 4), (71, 4, 0.5, 3),
+                                                         (72, 8, math.inf, 8)])
+def test_parallel_cpu_block_method_equals_block_reference(seed, block, stride_h, threads):
+    """The OpenMP block solver (the paper's parallel version) gives bitwise the sequential
+    block reference's psi, restarts and pops for any thread count (Sec. 2.7)."""
+    p = inputs.random_problem(seed, shape=(32, 24, 40), nsrc=3, obstacles=0.02)
+    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=block, stride=stride_h * p.h, stats=True)
+    got, st = oracle.block_fmm_parallel(p.F, p.h, p.sources, block=block, stride=stride_h * p.h,
+                                        threads=threads, stats=True)
+    assert np.array_equal(got, ref)
+    assert st["restarts"] == rs["restarts"] and st["pops"] == rs["pops"]
+    assert st["threads"] == threads
