@@ -104,9 +104,17 @@ def cpu_baseline(p, workload, seconds_target=15.0):
     oracle.fmm(F, p.h, s)
     dt = time.perf_counter() - t0
     pts = F.size
-    return {"value": round(pts / dt / 1e6, 4), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
+    base = {"value": round(pts / dt / 1e6, 4), "unit": "Mpts/s", "cores": 1, "kind": "oracle",
             "sample": f"single-heap FMM in FP64 on the {side}^3 box around the source cut from "
                       f"the same speed field ({pts} points, {dt:.1f} s, one thread)"}
+    # the paper's parallel CPU solver (block method, OpenMP over the blocks) on the same box
+    t0 = time.perf_counter()
+    _, st = oracle.block_fmm_parallel(F, p.h, s, block=16, stride=2 * p.h, stats=True)
+    dtp = time.perf_counter() - t0
+    par = {"value": round(pts / dtp / 1e6, 4), "unit": "Mpts/s", "threads": st["threads"],
+           "kind": "block method, OpenMP over the blocks of each step, FP64, 16^3 blocks, 2h",
+           "sample": f"the same {side}^3 box ({dtp:.1f} s, {st['restarts']} restarts)"}
+    return base, par
 
 
 WEIGHTS = os.path.join(ROOT, "paper_1811_00009_amd", "weights", "stride_mlp_b16.f32")
@@ -253,7 +261,7 @@ def run_single(args, torch, fmm):
                                   "max_abs_diff_vs_block16": diff, "within_fp32_bar": diff <= tol}
         del out8, fixed
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.workload)
+        out["cpu_baseline"], out["extra"]["cpu_parallel_block_solver"] = cpu_baseline(p, args.workload)
     return out
 
 
