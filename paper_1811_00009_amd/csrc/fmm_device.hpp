@@ -24,11 +24,12 @@ namespace fmmdev {
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));  // 16-byte copy unit
 
 // ---------------------------------------------------------------- tags
-// bits 0-1: category (Sec. 2.1 with KNOWN split as in Sec. 2.2); bit 2: the
-// point currently sits in the block's band array.
-constexpr uint8_t kFar = 0, kBand = 1, kKnownFix = 2, kKnownNew = 3;
-constexpr uint8_t kStatus = 3, kInBand = 4;
-__device__ __forceinline__ bool is_known(uint8_t t) { return (t & 2) != 0; }
+// bits 1-2: category (Sec. 2.1 with KNOWN split as in Sec. 2.2), ordered so that
+// KNOWN_FIX and KNOWN_NEW are the two largest; bit 0: the point currently sits
+// in the block's band array.
+constexpr uint8_t kFar = 0, kBand = 2, kKnownFix = 4, kKnownNew = 6;
+constexpr uint8_t kStatus = 6, kInBand = 1;
+__device__ __forceinline__ bool is_known(uint32_t t) { return t >= kKnownFix; }  // one compare
 
 // Faces: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z; the opposite face is f ^ 1.
 
@@ -233,13 +234,6 @@ struct MinPick {
     int slot;
 };
 
-// Locate_Min over the band: the lexicographic (psi, tile index) minimum.
-// Each lane reads 8 consecutive slots per 16-byte read and reduces them with
-// two shallow trees: the minimum value first, then the smallest key among its
-// slots holding that value, key = index << 16 | slot.  psi >= 0 (+0 only), so
-// IEEE bit patterns order like the values; the cross-lane step takes the
-// minimum value first (high then low word for FP64), then the minimum key
-// among the lanes holding it.  Returns the same result in every lane.
 // Minimum of two band values.  FP32: on the bit patterns (one integer min; psi >= +0
 // and +inf order like their bits).  FP64: a compare and select.
 __device__ __forceinline__ float val_min(float a, float b)
@@ -250,6 +244,60 @@ __device__ __forceinline__ double val_min(double a, double b) { return b < a ? b
 __device__ __forceinline__ bool val_eq(float a, float b) { return __float_as_uint(a) == __float_as_uint(b); }
 __device__ __forceinline__ bool val_eq(double a, double b) { return a == b; }
 
+// Minimum (value, key) over the 8 slots [c0 + 8 lane, c0 + 8 lane + 8) of one 512-slot chunk
+// of the band: two depth-3 trees, the minimum value first, then the smallest key
+// index << 16 | slot among the slots holding it.
+template <typename R>
+__device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, const uint16_t *g_band,
+                                               int cap, const FMM_LDS R *s_psi, int n, int c0,
+                                               int lane, R &m_out, uint32_t &k_out)
+{
+    const int base = c0 + lane * 8;
+    v4u raw;
+    if (c0 < cap) {
+        raw = *reinterpret_cast<const FMM_LDS v4u *>(s_band + base);
+    } else {
+        // the band's memory part (nontemporal loads: never merged with the LDS
+        // path into one flat access)
+        const uint32_t *g = reinterpret_cast<const uint32_t *>(g_band + base);
+        raw.x = __builtin_nontemporal_load(g);
+        raw.y = __builtin_nontemporal_load(g + 1);
+        raw.z = __builtin_nontemporal_load(g + 2);
+        raw.w = __builtin_nontemporal_load(g + 3);
+    }
+    const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+    uint32_t ids[8];
+    R vs[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const uint32_t sl = (uint32_t)(base + j);
+        const uint32_t id = (w4[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+        ids[j] = sl < (uint32_t)n ? id : 0u;  // tile point 0 (a corner) is never used: +inf
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) vs[j] = s_psi[ids[j]];
+    // minimum value of the 8 slots (tree of depth 3)
+    const R m = val_min(val_min(val_min(vs[0], vs[1]), val_min(vs[2], vs[3])),
+                        val_min(val_min(vs[4], vs[5]), val_min(vs[6], vs[7])));
+    // smallest key among the slots holding it
+    uint32_t ks[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        ks[j] = val_eq(vs[j], m) ? ((ids[j] << 16) | (uint32_t)(base + j)) : ~0u;
+    const uint32_t k0 = min(min(ks[0], ks[1]), min(ks[2], ks[3]));
+    const uint32_t k1 = min(min(ks[4], ks[5]), min(ks[6], ks[7]));
+    const uint32_t km = min(k0, k1);
+    m_out = m;
+    k_out = km;
+}
+
+// Locate_Min over the band: the lexicographic (psi, tile index) minimum.
+// Each lane reads 8 consecutive slots per 16-byte read and reduces them with
+// two shallow trees: the minimum value first, then the smallest key among its
+// slots holding that value, key = index << 16 | slot.  psi >= 0 (+0 only), so
+// IEEE bit patterns order like the values; the cross-lane step takes the
+// minimum value first (high then low word for FP64), then the minimum key
+// among the lanes holding it.  Returns the same result in every lane.
 template <typename R, int W>
 __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band,
                                                   const uint16_t *g_band, int cap,
@@ -259,42 +307,14 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
     const R inf = (R)INFINITY;
     R bv = inf;
     uint32_t bk = ~0u;
-    for (int c0 = wid * 512; c0 < n; c0 += 512 * W) {
-        const int base = c0 + lane * 8;
-        v4u raw;
-        if (c0 < cap) {
-            raw = *reinterpret_cast<const FMM_LDS v4u *>(s_band + base);
-        } else {
-            // the band's memory part (nontemporal loads: never merged with the LDS
-            // path into one flat access)
-            const uint32_t *g = reinterpret_cast<const uint32_t *>(g_band + base);
-            raw.x = __builtin_nontemporal_load(g);
-            raw.y = __builtin_nontemporal_load(g + 1);
-            raw.z = __builtin_nontemporal_load(g + 2);
-            raw.w = __builtin_nontemporal_load(g + 3);
-        }
-        const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
-        uint32_t ids[8];
-        R vs[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const uint32_t sl = (uint32_t)(base + j);
-            const uint32_t id = (w4[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
-            ids[j] = sl < (uint32_t)n ? id : 0u;  // tile point 0 (a corner) is never used: +inf
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) vs[j] = s_psi[ids[j]];
-        // minimum value of the 8 slots (tree of depth 3)
-        const R m = val_min(val_min(val_min(vs[0], vs[1]), val_min(vs[2], vs[3])),
-                            val_min(val_min(vs[4], vs[5]), val_min(vs[6], vs[7])));
-        // smallest key among the slots holding it
-        uint32_t ks[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-            ks[j] = val_eq(vs[j], m) ? ((ids[j] << 16) | (uint32_t)(base + j)) : ~0u;
-        const uint32_t k0 = min(min(ks[0], ks[1]), min(ks[2], ks[3]));
-        const uint32_t k1 = min(min(ks[4], ks[5]), min(ks[6], ks[7]));
-        const uint32_t km = min(k0, k1);
+    // the first chunk of each wave sets (bv, bk) directly; later chunks (bands of more
+    // than 512 * W slots) are merged in
+    int c0 = wid * 512;
+    if (c0 < n) band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk);
+    for (c0 += 512 * W; c0 < n; c0 += 512 * W) {
+        R m;
+        uint32_t km;
+        band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, m, km);
         const bool better = (m < bv) | (val_eq(m, bv) & (km < bk));
         bv = better ? m : bv;
         bk = better ? km : bk;
