@@ -48,9 +48,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, npoints_launch):
+PROFILED = {"block": 16, "waves_per_block": 1, "stride_h": 2.0}  # the configuration profiled
+
+
+def measured_traffic(workload, config=None):
     """HBM bytes per launch from committed rocprofv3 counter summaries, or None when
-    the summary is missing or was taken on different kernel sources."""
+    the summary is missing, was taken on different kernel sources, or the run's launch
+    configuration is not the profiled one."""
+    if config is not None and any(config.get(k) != v for k, v in PROFILED.items()):
+        return None
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -166,12 +172,12 @@ def parse():
     return ap.parse_args()
 
 
-def roofline(dtype, npts, loop_ms, workload):
+def roofline(dtype, npts, loop_ms, workload, config):
     algo_bytes = ALGO_BYTES_PER_POINT[dtype] * npts
     achieved = algo_bytes / (loop_ms / 1e3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-            "traffic": measured_traffic(workload, npts),
+            "traffic": measured_traffic(workload, config),
             "kernel": "k_persistent (restart loop)",
             "algorithmic_bytes_per_launch": algo_bytes,
             "kernel_ms": round(loop_ms, 3)}
@@ -224,7 +230,7 @@ def run_single(args, torch, fmm):
                     "block": args.block, "waves_per_block": args.waves,
                     "stride_h": args.stride_h, "sources": [list(s[:3]) for s in p.sources],
                     "stride_mode": "fixed"})
-    out["roofline"] = roofline(dtype, npts, loop_ms, args.workload)
+    out["roofline"] = roofline(dtype, npts, loop_ms, args.workload, out["config"])
     out["extra"] = {"restarts": st["restarts"], "pops": st["pops"],
                     "pops_per_s": round(st["pops"] / (st["loop_ms"] / 1e3), 1),
                     "march_calls": st["march_calls"], "tile_loads": st["tile_loads"],
@@ -307,7 +313,7 @@ def run_batched(args, torch, fmm):
                    {"workload": "batched_512", "solves": nsolve, "points": npts,
                     "sides": "uniform over {32, 48, ..., 192}", "block": B, "waves_per_block": W,
                     "stride_h": 2.0, "stride_mode": "fixed", "tuned_on": "fields 0-7"})
-    out["roofline"] = roofline("f32", npts, loop_ms, "batched_512")
+    out["roofline"] = roofline("f32", npts, loop_ms, "batched_512", out["config"])
     out["extra"] = {"sequential_Mpts_per_s": round(npts / seq / 1e6, 3),
                     "batched_over_sequential": round(seq / (wall / args.steps), 3),
                     "identical_to_sequential": same, "loop_ms": round(loop_ms, 3),
