@@ -119,6 +119,17 @@ struct Geo {
     static constexpr bool RHS_LDS = B <= 8;
 };
 
+// Tile index of the e-th point of the six boundary layers of the interior, e in [0, 6 B^2):
+// face f = e / B^2 in the order -x, +x, -y, +y, -z, +z, then the two in-face coordinates.
+template <int B>
+__device__ __forceinline__ int face_point(int e)
+{
+    constexpr int P = B + 2;
+    const int f = e / (B * B), r = e % (B * B);
+    const int a = r % B + 1, b = r / B + 1, l = (f & 1) ? B : 1;
+    return (f >> 1) == 0 ? l + P * (a + P * b) : ((f >> 1) == 1 ? a + P * (l + P * b) : a + P * (b + P * l));
+}
+
 template <typename R, int B, int W>
 struct Lds {
     static constexpr int T = Geo<B>::T;
@@ -291,8 +302,70 @@ __device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, c
     k_out = km;
 }
 
+// Minimum (value, key) over the S slots [S lane, S lane + S) of a band of n <= 64 S slots
+// held in LDS (S = 1, 2 or 4): the narrow form of band_chunk_min for small bands.
+template <typename R, int S>
+__device__ __forceinline__ void band_small_min(const FMM_LDS uint16_t *s_band, const FMM_LDS R *s_psi,
+                                               int n, int lane, R &m_out, uint32_t &k_out)
+{
+    const int base = lane * S;
+    uint32_t w[S > 1 ? S / 2 : 1];
+    if constexpr (S == 4) {
+        typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+        const v2u r = *reinterpret_cast<const FMM_LDS v2u *>(s_band + base);
+        w[0] = r.x;
+        w[1] = r.y;
+    } else if constexpr (S == 2) {
+        w[0] = *reinterpret_cast<const FMM_LDS uint32_t *>(s_band + base);
+    } else {
+        w[0] = s_band[base];
+    }
+    uint32_t ids[S];
+    R vs[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const uint32_t id = (w[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+        ids[j] = (uint32_t)(base + j) < (uint32_t)n ? id : 0u;  // tile point 0: +inf
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) vs[j] = s_psi[ids[j]];
+    R m = vs[0];
+#pragma unroll
+    for (int j = 1; j < S; ++j) m = val_min(m, vs[j]);
+    uint32_t km = ~0u;
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+        km = min(km, val_eq(vs[j], m) ? ((ids[j] << 16) | (uint32_t)(base + j)) : ~0u);
+    m_out = m;
+    k_out = km;
+}
+
+// Cross-lane step of Locate_Min within one wave: the minimum value over the lanes (high
+// then low word for FP64), then the smallest key among the lanes holding it -- usually one
+// lane does, and its key is read directly; equal values in several lanes take the
+// cross-lane minimum.  Returns (value bits high, low, key), wave-uniform.
+template <typename R>
+__device__ __forceinline__ void wave_pick(R bv, uint32_t bk, uint32_t &mh, uint32_t &ml, uint32_t &mk)
+{
+    const uint32_t vh = KeyBits<R>::hi(bv);
+    mh = wave_min_u32(vh);
+    bool tie = (vh == mh);
+    ml = 0;
+    if constexpr (sizeof(R) == 8) {
+        const uint32_t vl = KeyBits<R>::lo(bv);
+        ml = wave_min_u32(tie ? vl : ~0u);
+        tie = tie && (vl == ml);
+    }
+    const uint64_t tm = ballot(tie);
+    if (__builtin_popcountll(tm) == 1)
+        mk = (uint32_t)__builtin_amdgcn_readlane((int)bk, (int)__builtin_ctzll(tm));
+    else
+        mk = wave_min_u32(tie ? bk : ~0u);
+}
+
 // Locate_Min over the band: the lexicographic (psi, tile index) minimum.
-// Each lane reads 8 consecutive slots per 16-byte read and reduces them with
+// Each lane reads 8 consecutive slots per 16-byte read (1, 2 or 4 for a small band
+// marched by one wave) and reduces them with
 // two shallow trees: the minimum value first, then the smallest key among its
 // slots holding that value, key = index << 16 | slot.  psi >= 0 (+0 only), so
 // IEEE bit patterns order like the values; the cross-lane step takes the
@@ -307,35 +380,27 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
     const R inf = (R)INFINITY;
     R bv = inf;
     uint32_t bk = ~0u;
-    // the first chunk of each wave sets (bv, bk) directly; later chunks (bands of more
-    // than 512 * W slots) are merged in
-    int c0 = wid * 512;
-    if (c0 < n) band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk);
-    for (c0 += 512 * W; c0 < n; c0 += 512 * W) {
-        R m;
-        uint32_t km;
-        band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, m, km);
-        const bool better = (m < bv) | (val_eq(m, bv) & (km < bk));
-        bv = better ? m : bv;
-        bk = better ? km : bk;
+    if (W == 1 && n <= 256 && n <= cap) {
+        // a small band in LDS: 1, 2 or 4 slots per lane (n is wave-uniform)
+        if (n <= 64) band_small_min<R, 1>(s_band, s_psi, n, lane, bv, bk);
+        else if (n <= 128) band_small_min<R, 2>(s_band, s_psi, n, lane, bv, bk);
+        else band_small_min<R, 4>(s_band, s_psi, n, lane, bv, bk);
+    } else {
+        // the first chunk of each wave sets (bv, bk) directly; later chunks (bands of
+        // more than 512 * W slots) are merged in
+        int c0 = wid * 512;
+        if (c0 < n) band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk);
+        for (c0 += 512 * W; c0 < n; c0 += 512 * W) {
+            R m;
+            uint32_t km;
+            band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, m, km);
+            const bool better = (m < bv) | (val_eq(m, bv) & (km < bk));
+            bv = better ? m : bv;
+            bk = better ? km : bk;
+        }
     }
-    const uint32_t vh = KeyBits<R>::hi(bv);
-    const uint32_t mh = wave_min_u32(vh);
-    bool tie = (vh == mh);
-    uint32_t ml = 0;
-    if constexpr (sizeof(R) == 8) {
-        const uint32_t vl = KeyBits<R>::lo(bv);
-        ml = wave_min_u32(tie ? vl : ~0u);
-        tie = tie && (vl == ml);
-    }
-    // the key among the lanes holding the minimum: usually one lane does (read its key);
-    // equal values in several lanes take the cross-lane minimum
-    const uint64_t tm = ballot(tie);
-    uint32_t mk;
-    if (__builtin_popcountll(tm) == 1)
-        mk = (uint32_t)__builtin_amdgcn_readlane((int)bk, (int)__builtin_ctzll(tm));
-    else
-        mk = wave_min_u32(tie ? bk : ~0u);
+    uint32_t mh, ml, mk;
+    wave_pick<R>(bv, bk, mh, ml, mk);
     uint32_t h = mh, l = ml;
     if constexpr (W > 1) {
         __shared__ uint32_t s[16];
@@ -378,7 +443,7 @@ __device__ __forceinline__ R axis_candidate(R psq, R lo, bool klo, R hi, bool kh
 {
     const R inf = (R)INFINITY;
     const R a = klo ? lo : inf, b = khi ? hi : inf;
-    const R c = fmin(a, b);  // equal values: either side gives the same candidate
+    const R c = val_min(a, b);  // equal values: either side gives the same candidate
     return c < psq ? c : inf;
 }
 
@@ -399,6 +464,21 @@ __device__ __forceinline__ double bound_in<double>(double bound) { return bound;
 
 __device__ __forceinline__ float root2(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double root2(double x) { return __builtin_sqrt(x); }
+
+// x / 3, rounded as the IEEE division.  FP32: the product with RN(1/3), corrected by
+// one fused multiply-add on the exact residual x - 3 q0; for every finite binary32 x
+// this is the correctly rounded quotient (checked over all non-negative values,
+// denormals included; the rounding is odd-symmetric), and x = inf stays inf.
+// FP64: the division itself.
+__device__ __forceinline__ float div3(float x)
+{
+    const float c = 0x1.555556p-2f;  // RN(1/3)
+    const float q0 = x * c;
+    const float r = __builtin_fmaf(-3.0f, q0, x);
+    const float q1 = __builtin_fmaf(r, c, q0);
+    return q0 == INFINITY ? q0 : q1;
+}
+__device__ __forceinline__ double div3(double x) { return x / 3.0; }
 
 template <typename R>
 __device__ __forceinline__ R quad_root(R c0, R c1, R c2, R rhs)
@@ -425,7 +505,7 @@ __device__ __forceinline__ R quad_root(R c0, R c1, R c2, R rhs)
             R s2b = u1 * u1 + u2 * u2;
             R disc3 = s1b * s1b - (R)3 * (s2b - rhs);
             if (disc3 < 0) disc3 = 0;
-            t = v0 + (s1b + root2(disc3)) / (R)3;
+            t = v0 + div3(s1b + root2(disc3));
         }
     }
     return t;

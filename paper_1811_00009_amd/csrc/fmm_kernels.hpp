@@ -99,10 +99,11 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
 // every neighbour whose ghost layer meets the updated boundary points.
 //
 // One accepted point costs two LDS round trips for Locate_Min (a 16-byte read
-// of 8 band slots per lane, then the 8 psi values) and two for Update_Neighbors
-// (lanes 0-5 read the neighbour's tag and psi while lane 6 reads the accepted
-// point's tag and lane 7 the band's last slot; then the six stencils), with the
-// h^2/F^2 load of every neighbour issued ahead of both.
+// of 8 band slots per lane, then the 8 psi values) and one or two for
+// Update_Neighbors (lanes 0-5 read the neighbour's tag and psi while lane 6
+// reads the accepted point's tag and lane 7 the band's last slot; the six
+// stencils in the same round trip when h^2/F^2 is in LDS, else in a second one
+// that covers the h^2/F^2 load from device memory, issued first).
 template <typename R, int B, int W>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
                             int c, char *smem, unsigned long long &pops_acc, bool &a_out,
@@ -155,7 +156,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     const int dI = (lane == 1) - (lane == 0), dJ = (lane == 3) - (lane == 2),
               dK = (lane == 5) - (lane == 4);
     const int dOff = dI + P * (dJ + P * dK);
-    uint32_t fb_acc = 0;  // faces of Upsilon touched by this lane's updates
+    constexpr int kMid = (B / 2) * (1 + P + P * P);  // an interior point of the tile
     bool active = true;
     R exit_min = inf;
     int npops = 0;
@@ -183,6 +184,14 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         n -= 1;  // Remove_Min: the last slot moves into the hole (lane 7 below)
         // Update_Neighbors(p): lanes 0-5 take the six face neighbours (interior only)
         if (wid == 0) {
+            // h^2/F^2 of the lane's neighbour from device memory, issued before anything
+            // else of the step (the index is clamped to the tile; unused when the
+            // neighbour is not interior)
+            R rhs_mem = (R)0;
+            if constexpr (!Gm::RHS_LDS) {
+                const int ql = p + dOff;
+                rhs_mem = g_rhs[ql < 0 ? 0 : (ql > T - 1 ? T - 1 : ql)];
+            }
             const uint32_t up = (uint32_t)p;
             const int pi = (int)(up % P), pj = (int)((up / P) % P), pk = (int)(up / (P * P));
             const int qi = pi + dI, qj = pj + dJ, qk = pk + dK;
@@ -192,10 +201,29 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             R rhs = (R)0;
             if (inb) {
                 if constexpr (Gm::RHS_LDS) rhs = s_rhs[q];
-                else rhs = g_rhs[q];
+                else rhs = rhs_mem;
             }
             const uint8_t tq = s_tag[q];  // lane 6 reads the accepted point's own tag
             const R psq = s_psi[q];
+            // With h^2/F^2 in LDS (small blocks) the stencil of q is read in the same
+            // round trip: its points are not written in this step (the six neighbours are
+            // pairwise not face-adjacent), except p's tag, which lane 6 turns KNOWN below;
+            // p is taken as known instead.  Lanes without a neighbour read around an
+            // interior point of the tile (unused).  With h^2/F^2 in device memory the
+            // stencil is read after the check below, while that load is in flight.
+            R lo[3], hi[3];
+            uint32_t tlo[3], thi[3];
+            if constexpr (Gm::RHS_LDS) {
+                const int qs = inb ? q : kMid;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+                    lo[ax] = s_psi[qs - off];
+                    hi[ax] = s_psi[qs + off];
+                    tlo[ax] = s_tag[qs - off];
+                    thi[ax] = s_tag[qs + off];
+                }
+            }
             // Remove_Min: lane 7 moves the band's last slot into the hole.  The branch on
             // the wave-uniform n < cap keeps the usual all-LDS case free of any wait on
             // device memory (the h^2/F^2 load above stays in flight until the solve).
@@ -215,27 +243,33 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
                 s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
             bool ins = false;
-            uint32_t fb = 0;
             if (inb && (tq & kStatus) != kKnownFix && psq > mp.v) {
                 R c[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
-                    const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
-                    const R lo = s_psi[q - off], hi = s_psi[q + off];
-                    // p itself reads as known: lane 6 wrote its tag above, and one
-                    // wave's LDS accesses complete in program order
-                    const bool klo = is_known(s_tag[q - off]);
-                    const bool khi = is_known(s_tag[q + off]);
-                    c[ax] = axis_candidate<R>(psq, lo, klo, hi, khi);
+                    bool klo, khi;
+                    if constexpr (Gm::RHS_LDS) {
+                        // p is q's low neighbour for the + directions (odd lanes) and its
+                        // high neighbour for the - directions, on the lane's own axis
+                        const bool own = ax == (lane >> 1);
+                        klo = is_known(tlo[ax]) || (own && (lane & 1));
+                        khi = is_known(thi[ax]) || (own && !(lane & 1));
+                    } else {
+                        const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+                        lo[ax] = s_psi[q - off];
+                        hi[ax] = s_psi[q + off];
+                        // p itself reads as known: lane 6 wrote its tag above, and one
+                        // wave's LDS accesses complete in program order
+                        klo = is_known(s_tag[q - off]);
+                        khi = is_known(s_tag[q + off]);
+                    }
+                    c[ax] = axis_candidate<R>(psq, lo[ax], klo, hi[ax], khi);
                 }
                 const R t = quad_root<R>(c[0], c[1], c[2], rhs);
                 if (t < psq) {
                     s_psi[q] = t;
                     s_tag[q] = kBand | kInBand;
                     ins = !(tq & kInBand);
-                    fb = (uint32_t)(qi == 1) | ((uint32_t)(qi == B) << 1) |
-                         ((uint32_t)(qj == 1) << 2) | ((uint32_t)(qj == B) << 3) |
-                         ((uint32_t)(qk == 1) << 4) | ((uint32_t)(qk == B) << 5);
                 }
             }
             const uint64_t bal = ballot(ins);
@@ -251,7 +285,6 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            fb_acc |= fb;
             if constexpr (W > 1) {
                 if (lane == 0) s_bc[0] = n;
             }
@@ -267,9 +300,31 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         }
     }
 
+    // Upsilon on the faces: a face is touched exactly when one of its boundary points got a
+    // smaller value (every update of Update_Neighbors is a strict decrease, and nothing else
+    // writes psi in the march); the block's tile in memory still holds the values the march
+    // started from
+    constexpr int NF = 6 * B * B, FPER = (NF + NT - 1) / NT;
+    uint32_t mine = 0;
+#pragma unroll 4
+    for (int k = 0; k < FPER; ++k) {
+        const int e = tid + k * NT;
+        if (e < NF) {
+            const int t = face_point<B>(e);
+            if (s_psi[t] < g_psi[t]) mine |= 1u << (e / (B * B));
+        }
+    }
     uint32_t dirty = 0;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) dirty |= (uint32_t)__builtin_amdgcn_readlane((int)fb_acc, k);
+    for (int f = 0; f < 6; ++f) dirty |= ballot((mine >> f) & 1u) ? 1u << f : 0u;
+    if constexpr (W > 1) {
+        __shared__ uint32_t s_dirty[1];
+        if (tid == 0) s_dirty[0] = 0u;
+        __syncthreads();
+        if (lane == 0 && dirty) atomicOr(s_dirty, dirty);
+        __syncthreads();
+        dirty = s_dirty[0];
+    }
     // LDS -> tile
     copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<v4u *>(g_psi),
                                                reinterpret_cast<const FMM_LDS v4u *>(s_psi), tid);
