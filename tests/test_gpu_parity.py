@@ -226,13 +226,34 @@ def test_band_beyond_lds_capacity_spills_exactly(fmm_lib, dtype):
     ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=16, stride=3.5 * p.h, dtype=dtype,
                                stats=True)
     for cap in (512, 0):
-        got, st = _run(fmm_lib, p, dtype, block=16, stride=3.5 * p.h, band_lds_cap=cap)
-        assert np.array_equal(got, ref)
-        assert st["pops"] == rs["pops"] and st["restarts"] == rs["restarts"]
+        for waves in (1, 2):
+            got, st = _run(fmm_lib, p, dtype, block=16, stride=3.5 * p.h, band_lds_cap=cap,
+                           waves_per_block=waves)
+            assert np.array_equal(got, ref)
+            assert st["pops"] == rs["pops"] and st["restarts"] == rs["restarts"]
     wide = inputs.smooth_sine(64, dtype=dtype)
     ref = oracle.block_fmm(wide.F, wide.h, wide.sources, block=16, stride=8 * wide.h, dtype=dtype)
     got, _ = _run(fmm_lib, wide, dtype, block=16, stride=8 * wide.h, band_lds_cap=512)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("waves", [2, 4])
+def test_multi_wave_march_is_bitwise_the_block_reference(fmm_lib, dtype, waves):
+    """A march by several waves (Locate_Min split over the waves by 512-slot chunks, the
+    update on wave 0): bitwise the block reference, with the same pop count, on exact ties
+    (constant speed, centre source), on small bands (8^3 blocks), and on bands of more than
+    512 slots (a large stride)."""
+    cases = [(inputs.paper_case(1, 64), 16, 2.0), (inputs.paper_case(1, 64), 8, math.inf),
+             (inputs.random_problem(360, shape=(48, 32, 32), nsrc=4, dtype=dtype,
+                                    obstacles=0.02), 16, 2.0),
+             (inputs.smooth_sine(64, dtype=dtype), 16, 8.0)]
+    for p, block, sh in cases:
+        ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=block, stride=sh * p.h,
+                                   dtype=dtype, stats=True)
+        got, st = _run(fmm_lib, p, dtype, block=block, stride=sh * p.h, waves_per_block=waves)
+        assert np.array_equal(got, ref), (block, sh)
+        assert st["pops"] == rs["pops"] and st["restarts"] == rs["restarts"]
 
 
 # ------------------------------------------------------------------ the paper's test cases
