@@ -289,8 +289,12 @@ def run_batched(args, torch, fmm):
     outs = [torch.empty_like(p.F) for p in probs]
 
     def step():
-        return fmm.solve_batched(batch, block=B, waves_per_block=W, outs=outs,
-                                 with_stats=True)[1][0]
+        per = fmm.solve_batched(batch, block=B, waves_per_block=W, outs=outs,
+                                with_stats=True)[1]
+        st = dict(per[0])  # times and launch shape are the launch's, the same in every row
+        st["pops"] = sum(s["pops"] for s in per)
+        st["restarts"] = max(s["restarts"] for s in per)
+        return st
 
     stats, wall = timed(step, args.steps, args.warmup, "batched")
     ms_per_step = wall / args.steps * 1e3
@@ -314,7 +318,9 @@ def run_batched(args, torch, fmm):
                     "sides": "uniform over {32, 48, ..., 192}", "block": B, "waves_per_block": W,
                     "stride_h": 2.0, "stride_mode": "fixed", "tuned_on": "fields 0-7"})
     out["roofline"] = roofline("f32", npts, loop_ms, "batched_512", out["config"])
-    out["extra"] = {"sequential_Mpts_per_s": round(npts / seq / 1e6, 3),
+    out["extra"] = {"pops": stats[-1]["pops"], "max_restarts": stats[-1]["restarts"],
+                    "pops_per_s": round(stats[-1]["pops"] / (loop_ms / 1e3), 1),
+                    "sequential_Mpts_per_s": round(npts / seq / 1e6, 3),
                     "batched_over_sequential": round(seq / (wall / args.steps), 3),
                     "identical_to_sequential": same, "loop_ms": round(loop_ms, 3),
                     "grid": stats[-1]["grid"], "kernel_hash": kernel_source_hash()}
