@@ -475,7 +475,8 @@ __device__ __forceinline__ int band_bin(int nb)
 // one of 4 bins by its expected work est (longest first), and add it to the restart
 // features.  One thread per block.
 template <typename R>
-__device__ void append_next(const KParams<R> &kp, int c, int64_t r, int64_t ib, int est, int nb)
+__device__ void append_next(const KParams<R> &kp, int c, int64_t r, int64_t ib, int est, int nb,
+                            unsigned long long *lfeat)
 {
     Ctl *ctl = kp.ctl;
     int32_t *next = c ? kp.list0 : kp.list1;
@@ -484,11 +485,19 @@ __device__ void append_next(const KParams<R> &kp, int c, int64_t r, int64_t ib, 
     if (pos < kp.nblk) next[(int64_t)k * kp.nblk + pos] = (int32_t)ib;
     else raise_error(ctl, kErrList);  // cannot happen: one entry per block
     atomicAdd(&ctl->n_list[c ^ 1], 1);
-    if (kp.want_features) {
-        atomicAdd(&ctl->feat[c ^ 1][band_bin(nb)], 1ull);
-        atomicAdd(&ctl->feat[c ^ 1][8], (unsigned long long)((double)kp.fmean[ib] * kFixScale + 0.5));
+    if (kp.want_features) {  // the work-group's sums, added to ctl->feat by flush_features
+        lfeat[band_bin(nb)] += 1ull;
+        lfeat[8] += (unsigned long long)((double)kp.fmean[ib] * kFixScale + 0.5);
     }
     if (kp.nprob > 1) atomicMax(&kp.prob_lastr[kp.blk_prob[ib]], (int)r);
+}
+
+// The restart features a work-group gathered in one phase (integer sums, so the order in
+// which work-groups add them does not matter), one atomic per nonzero entry.
+__device__ __forceinline__ void flush_features(Ctl *ctl, int cn, const unsigned long long *lfeat)
+{
+    for (int k = 0; k < 9; ++k)
+        if (lfeat[k]) atomicAdd(&ctl->feat[cn][k], lfeat[k]);
 }
 
 // Marching step of restart r: blocks of the march list list[r & 1] are taken
@@ -509,7 +518,9 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
     const int32_t *cur = c ? kp.list1 : kp.list0;
     const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __shared__ int s_bins[3];
+    __shared__ unsigned long long s_feat[9];
     if (tid < 3) s_bins[tid] = __hip_atomic_load(&ctl->bin_n[c][tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tid < 9) s_feat[tid] = 0ull;
     __syncthreads();
     const int bn0 = s_bins[0], bn1 = s_bins[1], bn2 = s_bins[2];
     __shared__ int s_item[1];
@@ -552,7 +563,7 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
                 if ((double)bm > pd.width) kp.A[ib] = 0;
                 else {
                     const int nb = kp.band_n[ib];
-                    append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nb), nb);
+                    append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nb), nb, s_feat);
                 }
             }
             continue;
@@ -567,8 +578,9 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         bool a;
         int nb, np;
         march_block<R, B, W>(kp, ib, pd, bound, c, smem, pops, a, nb, np);
-        if (tid == 0 && a) append_next<R>(kp, c, r, ib, max(np, nb), nb);
+        if (tid == 0 && a) append_next<R>(kp, c, r, ib, max(np, nb), nb, s_feat);
     }
+    if (tid == 0 && kp.want_features) flush_features(ctl, c ^ 1, s_feat);
     if (tid == 0 && mcalls) {
         atomicAdd(&ctl->pops, pops);
         atomicAdd(&ctl->rpops[c], pops);
@@ -590,6 +602,8 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
     Ctl *ctl = kp.ctl;
     const int nx = __hip_atomic_load(&ctl->x_n[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __shared__ int s_item[1];
+    __shared__ unsigned long long s_feat[9];
+    if (tid < 9) s_feat[tid] = 0ull;  // ordered before use by the barrier in the loop
     unsigned long long xcalls = 0;
     for (;;) {
         if (tid == 0) s_item[0] = atomicAdd(&ctl->x_head[c], 1);
@@ -612,36 +626,42 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
         ++xcalls;
         if (tid == 0) {
             if (an && !a0) {
-                append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nn), nn);
+                append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nn), nn, s_feat);
             } else if (a0 && kp.want_features && band_bin(nn) != band_bin(n0)) {
-                atomicAdd(&ctl->feat[c ^ 1][band_bin(n0)], ~0ull);  // -1
-                atomicAdd(&ctl->feat[c ^ 1][band_bin(nn)], 1ull);
+                s_feat[band_bin(n0)] += ~0ull;  // -1 (modulo 2^64, like the totals)
+                s_feat[band_bin(nn)] += 1ull;
             }
         }
     }
+    if (tid == 0 && kp.want_features) flush_features(ctl, c ^ 1, s_feat);
     if (tid == 0 && xcalls) atomicAdd(&ctl->exchange_calls, xcalls);
 }
 
 // ---------------------------------------------------------------- stride network
-// m = exp(ln(1/4) + sigmoid(z) ln 32) for the standardised features, FP32,
-// evaluated identically by every work-group.
+// m = exp(ln(1/4) + sigmoid(z) ln 32) for the standardised features, FP32, evaluated by
+// each wave on its lanes: lane o (o < 32) computes hidden unit o of each layer from its
+// own row of weights, and reads the other units from their lanes.  Every sum runs in the
+// same order as the layers' definition, so every work-group gets the same m.
 __device__ float mlp_multiplier(const float *blob, const float *raw)
 {
     const float *W1 = blob, *b1 = W1 + 32 * 12, *W2 = b1 + 32, *b2 = W2 + 32 * 32, *W3 = b2 + 32,
                 *b3 = W3 + 32, *mu = b3 + 1, *sd = mu + 12;
-    float x[12], h1[32];
+    const int o = (int)(threadIdx.x & 31);
+    float x[12];
+#pragma unroll
     for (int i = 0; i < 12; ++i) x[i] = (raw[i] - mu[i]) / sd[i];
-    for (int o = 0; o < 32; ++o) {
-        float s = b1[o];
-        for (int i = 0; i < 12; ++i) s += W1[o * 12 + i] * x[i];
-        h1[o] = s > 0.f ? s : 0.f;
-    }
+    float s1 = b1[o];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s1 += W1[o * 12 + i] * x[i];
+    const float h1 = s1 > 0.f ? s1 : 0.f;
+    float s2 = b2[o];
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+        s2 += W2[o * 32 + i] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1), i));
+    const float t = W3[o] * (s2 > 0.f ? s2 : 0.f);
     float z = b3[0];
-    for (int o = 0; o < 32; ++o) {
-        float s = b2[o];
-        for (int i = 0; i < 32; ++i) s += W2[o * 32 + i] * h1[i];
-        z += W3[o] * (s > 0.f ? s : 0.f);
-    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) z += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), k));
     const float sig = 1.0f / (1.0f + expf(-z));
     const float m = expf((float)kLogMinMult + sig * (float)kLogSpanMult);
     return m;
