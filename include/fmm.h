@@ -228,6 +228,19 @@ int fmm_mlp_train(float *params_dev, const float *x_dev, const float *t_dev, int
 int fmm_selftest_wave_min(const uint32_t *in_dev, uint32_t *out_dev, int32_t nwaves,
                           void *hip_stream);
 
+/* Locate_Min (Alg. 4: the band point of least psi, ties to the lower tile index) of a
+   march by one wave, on a given band: psi_dev holds the (B+2)^3 tile values of one block
+   (dtype; entry 0, the tile corner, is never a band point and reads as +inf) and band_dev
+   n distinct tile indices in [1, (B+2)^3), 1 <= n < (B+2)^3.  The first `cap` slots (0 or
+   a multiple of 512; 0 = as many as a march keeps there) are staged in LDS as in a march,
+   the rest are read from device memory.  Writes the picked value to val_out_dev[0] (dtype) and its tile
+   index and band slot to idx_out_dev[0], idx_out_dev[1].  Synchronous on hip_stream;
+   allocates a padded copy of the band.  FMM_EINVAL for null pointers, an unsupported
+   dtype or block size (4, 8, 16), n out of range or a bad cap. */
+int fmm_selftest_band_argmin(int dtype, int32_t block, const void *psi_dev,
+                             const uint16_t *band_dev, int32_t n, int32_t cap,
+                             void *val_out_dev, int32_t *idx_out_dev, void *hip_stream);
+
 const char *fmm_strerror(int code);
 const char *fmm_last_error_detail(void);
 /* Library version string. */

@@ -532,6 +532,37 @@ void tune_file_store(const char *path, const std::string &key, const fmm_tuning 
 } // namespace
 
 // ============================================================================ C ABI
+namespace {
+template <typename R, int B>
+int argmin_probe(const void *psi_dev, const uint16_t *band_dev, int32_t n, int32_t cap,
+                 void *val_out_dev, int32_t *idx_out_dev, hipStream_t st)
+{
+    using Gm = fmmdev::Geo<B>;
+    if (n < 1 || n > Gm::T - 1) return fail(FMM_EINVAL, "fmm_selftest_band_argmin: n out of range");
+    const int c = cap > 0 && cap < Gm::BANDC ? cap : Gm::BANDC;
+    std::vector<uint16_t> hb((size_t)n);
+    HIPCHK(hipMemcpyAsync(hb.data(), band_dev, sizeof(uint16_t) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (uint16_t t : hb)
+        if (t < 1 || t >= Gm::T) return fail(FMM_EINVAL, "fmm_selftest_band_argmin: band index out of the tile");
+    // the band array padded to whole 512-slot chunks, as in the workspace
+    uint16_t *pad = nullptr;
+    HIPCHK(hipMalloc(&pad, sizeof(uint16_t) * Gm::BAND));
+    hipError_t e = hipMemsetAsync(pad, 0, sizeof(uint16_t) * Gm::BAND, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(pad, band_dev, sizeof(uint16_t) * n, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) {
+        fmmdev::k_argmin_probe<R, B><<<1, 64, fmmdev::Lds<R, B, 1>::bytes, st>>>(
+            (const R *)psi_dev, pad, n, c, (R *)val_out_dev, idx_out_dev);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(pad);
+    HIPCHK(e);
+    return 0;
+}
+} // namespace
+
 extern "C" {
 
 void fmm_options_default(fmm_options *opt)
@@ -674,6 +705,32 @@ int fmm_selftest_wave_min(const uint32_t *in_dev, uint32_t *out_dev, int32_t nwa
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(st));
     return 0;
+}
+
+
+int fmm_selftest_band_argmin(int dtype, int32_t block, const void *psi_dev, const uint16_t *band_dev,
+                             int32_t n, int32_t cap, void *val_out_dev, int32_t *idx_out_dev,
+                             void *hip_stream)
+{
+    if (!psi_dev || !band_dev || !val_out_dev || !idx_out_dev)
+        return fail(FMM_EINVAL, "fmm_selftest_band_argmin: null pointer");
+    if (cap < 0 || cap % 512)
+        return fail(FMM_EINVAL, "fmm_selftest_band_argmin: cap must be a non-negative multiple of 512");
+    hipStream_t st = (hipStream_t)hip_stream;
+    try {
+        if (dtype == FMM_F32) {
+            if (block == 4) return argmin_probe<float, 4>(psi_dev, band_dev, n, cap, val_out_dev, idx_out_dev, st);
+            if (block == 8) return argmin_probe<float, 8>(psi_dev, band_dev, n, cap, val_out_dev, idx_out_dev, st);
+            if (block == 16) return argmin_probe<float, 16>(psi_dev, band_dev, n, cap, val_out_dev, idx_out_dev, st);
+        } else if (dtype == FMM_F64) {
+            if (block == 4) return argmin_probe<double, 4>(psi_dev, band_dev, n, cap, val_out_dev, idx_out_dev, st);
+            if (block == 8) return argmin_probe<double, 8>(psi_dev, band_dev, n, cap, val_out_dev, idx_out_dev, st);
+            if (block == 16) return argmin_probe<double, 16>(psi_dev, band_dev, n, cap, val_out_dev, idx_out_dev, st);
+        }
+        return fail(FMM_EINVAL, "fmm_selftest_band_argmin: dtype or block size not supported");
+    } catch (const std::exception &ex) {
+        return fail(FMM_EHIP, std::string("fmm_selftest_band_argmin: ") + ex.what());
+    }
 }
 
 const char *fmm_strerror(int code)

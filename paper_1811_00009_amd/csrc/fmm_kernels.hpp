@@ -916,4 +916,29 @@ __global__ void k_wave_min(const uint32_t *in, uint32_t *out, int nwaves)
     if (threadIdx.x == 0) out[wv] = m;
 }
 
+// Locate_Min of a march by one wave on a given band (a test probe): the tile values and
+// the band are staged as march_block stages them -- the first cap slots in LDS, the rest
+// read from the padded band array in memory -- and the pick is written out.  The tile's
+// corner 0 is never a band point and reads as +inf, as in every tile.
+template <typename R, int B>
+__global__ void __launch_bounds__(64) k_argmin_probe(const R *psi, const uint16_t *band, int n,
+                                                     int cap, R *vout, int32_t *iout)
+{
+    using L = Lds<R, B, 1>;
+    using Gm = Geo<B>;
+    extern __shared__ __align__(16) char smem[];
+    FMM_LDS char *lds = (FMM_LDS char *)smem;
+    FMM_LDS R *s_psi = reinterpret_cast<FMM_LDS R *>(lds + L::psi_off);
+    FMM_LDS uint16_t *s_band = reinterpret_cast<FMM_LDS uint16_t *>(lds + L::band_off);
+    for (int t = threadIdx.x; t < Gm::T; t += 64) s_psi[t] = t == 0 ? (R)INFINITY : psi[t];
+    for (int k = threadIdx.x; k < Gm::BANDC; k += 64) s_band[k] = k < n ? band[k] : (uint16_t)0;
+    __syncthreads();
+    const MinPick<R> mp = band_argmin<R, 1>(s_band, band, cap, s_psi, n);
+    if (threadIdx.x == 0) {
+        vout[0] = mp.v;
+        iout[0] = mp.idx;
+        iout[1] = mp.slot;
+    }
+}
+
 } // namespace fmmdev

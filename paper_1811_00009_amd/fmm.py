@@ -105,6 +105,8 @@ def load():
     lib.fmm_mlp_train.restype = C.c_int
     lib.fmm_selftest_wave_min.argtypes = [vp, vp, i32, vp]
     lib.fmm_selftest_wave_min.restype = C.c_int
+    lib.fmm_selftest_band_argmin.argtypes = [i32, i32, vp, vp, i32, i32, vp, vp, vp]
+    lib.fmm_selftest_band_argmin.restype = C.c_int
     lib.fmm_strerror.argtypes = [C.c_int]
     lib.fmm_strerror.restype = C.c_char_p
     lib.fmm_last_error_detail.argtypes = []
@@ -303,6 +305,26 @@ def selftest_wave_min(x):
     _check(load().fmm_selftest_wave_min(x.data_ptr(), out.data_ptr(), nw, _stream()),
            "fmm_selftest_wave_min")
     return out
+
+
+def selftest_band_argmin(psi_tile, band, block: int, cap: int = 0):
+    """Locate_Min of a march by one wave on a given band: psi_tile is the (B+2)^3 tile of
+    one block (float32 or float64 GPU tensor), band the tile indices (int16 GPU tensor).
+    Returns (value, tile index, slot)."""
+    import torch
+    _check_tensor(psi_tile, "psi_tile")
+    _check_tensor(band, "band")
+    if band.dtype != torch.int16:
+        raise TypeError("band must be an int16 tensor of tile indices")
+    dt = _dtype_code(psi_tile)
+    val = torch.empty(1, dtype=psi_tile.dtype, device=psi_tile.device)
+    idx = torch.empty(2, dtype=torch.int32, device=psi_tile.device)
+    _check(load().fmm_selftest_band_argmin(dt, int(block), psi_tile.data_ptr(), band.data_ptr(),
+                                           int(band.numel()), int(cap), val.data_ptr(),
+                                           idx.data_ptr(), _stream()),
+           "fmm_selftest_band_argmin")
+    i = idx.cpu().tolist()
+    return val.item(), i[0], i[1]
 
 
 def trace_rows(trace_tensor, count: int):

@@ -66,6 +66,38 @@ def test_wave_min_selftest(fmm_lib):
     assert np.array_equal(got, vals.min(axis=1))
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("block", [8, 16])
+def test_locate_min_on_given_bands(fmm_lib, dtype, block):
+    """Locate_Min of a march by one wave -- 1, 2 or 4 slots per lane for bands of at most
+    64, 128 or 256 slots in LDS, 8 per lane and 512-slot chunks otherwise, slots past the
+    LDS capacity read from memory -- against the lexicographic (psi, tile index) minimum
+    of numpy, on bands of every size class with many equal values."""
+    import torch
+    T = (block + 2) ** 3
+    rng = np.random.default_rng(block)
+    sizes = [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025,
+             2047, T - 1]
+    for n in [m for m in sizes if m <= T - 1]:
+        for cap in (0, 512):
+            for trial in range(2):
+                psi = (rng.integers(0, 40, size=T) * 0.125 + 1.0).astype(dtype)
+                if trial:
+                    psi[rng.random(T) < 0.1] = np.inf
+                psi[0] = np.inf
+                band = rng.choice(np.arange(1, T), size=n, replace=False).astype(np.int16)
+                # a band point is never FAR, so a band's minimum is finite (empty slots
+                # read the tile corner, +inf)
+                psi[int(band[0])] = min(psi[int(band[0])], dtype(6.0))
+                vals = psi[band.astype(np.int64)]
+                k = int(np.lexsort((band, vals))[0])
+                v, idx, slot = fmm_lib.selftest_band_argmin(torch.from_numpy(psi).cuda(),
+                                                            torch.from_numpy(band).cuda(),
+                                                            block, cap)
+                assert (idx, slot) == (int(band[k]), k), (n, cap, trial)
+                assert v == vals[k] or (np.isinf(v) and np.isinf(vals[k]))
+
+
 # ------------------------------------------------------------------ single block (Sec. 3.2)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n,block", [(16, 16), (8, 8), (4, 4)])
