@@ -35,20 +35,22 @@ __device__ __forceinline__ bool is_known(uint32_t t) { return t >= kKnownFix; } 
 
 // ---------------------------------------------------------------- control block
 struct Ctl {
-    unsigned bar_count;            // grid barrier arrivals
-    unsigned bar_gen;              // grid barrier generation
-    int abort;                     // first error code raised on the device (0 = none)
-    int pad0;
-    int n_list[2];                 // march-list sizes, by restart parity
-    int q_head[2];                 // march work-queue heads, by restart parity
-    int bin_n[2][4];               // march-list sizes per work bin, by restart parity
-    int x_n[2];                    // exchange-list sizes, by restart parity
-    int x_head[2];                 // exchange work-queue heads, by restart parity
-    unsigned long long pops, march_calls, exchange_calls, tile_loads;
-    unsigned long long rpops[2];   // pops of the current restart, by parity
-    unsigned long long rmin[2];    // bits of the smallest value popped in the restart (traces)
-    unsigned long long feat[2][10];// band-size bins (8), sum of block mean speed (2^20 fixed
-                                   // point), unused; by parity of the list being built
+    // Counters that every work-group touches in each restart sit on 128-byte lines of
+    // their own, so the barrier's arrivals, its polled generation, the queue heads and
+    // the list appends do not contend for one line.
+    alignas(128) unsigned bar_count;  // grid barrier arrivals
+    alignas(128) unsigned bar_gen;    // grid barrier generation (polled)
+    int abort;                        // first error code raised on the device (0 = none)
+    alignas(128) int q_head[2];       // march work-queue heads, by restart parity
+    int x_head[2];                    // exchange work-queue heads, by restart parity
+    alignas(128) int n_list[2];       // march-list sizes, by restart parity
+    int bin_n[2][4];                  // march-list sizes per work bin, by restart parity
+    int x_n[2];                       // exchange-list sizes, by restart parity
+    alignas(128) unsigned long long pops, march_calls, exchange_calls, tile_loads;
+    unsigned long long rpops[2];      // pops of the current restart, by parity
+    unsigned long long rmin[2];       // bits of the smallest value popped in the restart (traces)
+    alignas(128) unsigned long long feat[2][10]; // band-size bins (8), sum of block mean speed
+                                      // (2^20 fixed point), unused; by parity of the list
     long long restarts;
     double final_bound;
 };

@@ -510,7 +510,7 @@ __device__ __forceinline__ void flush_features(Ctl *ctl, int cn, const unsigned 
 // that stays active goes on the next march list right away (an exchange can
 // only activate a block, never deactivate it).
 template <typename R, int B, int W>
-__device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem)
+__device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem, int G, int w)
 {
     const int c = (int)(r & 1);
     const int tid = threadIdx.x;
@@ -525,11 +525,17 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
     const int bn0 = s_bins[0], bn1 = s_bins[1], bn2 = s_bins[2];
     __shared__ int s_item[1];
     unsigned long long pops = 0, mcalls = 0, loads = 0;
-    for (;;) {
-        if (tid == 0) s_item[0] = atomicAdd(&ctl->q_head[c], 1);
-        __syncthreads();
-        const int item = s_item[0];
-        __syncthreads();
+    // item w goes to work-group w without touching the queue; items from G on come from
+    // the queue, which a list no longer than the grid never reaches
+    for (int it = 0;; ++it) {
+        int item = w;
+        if (it > 0) {
+            if (G >= ncur) break;
+            if (tid == 0) s_item[0] = G + atomicAdd(&ctl->q_head[c], 1);
+            __syncthreads();
+            item = s_item[0];
+            __syncthreads();
+        }
         if (item >= ncur) break;
         // bins in order: the blocks with the most expected work first
         int k = 0, off = item;
@@ -603,13 +609,18 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
     const int nx = __hip_atomic_load(&ctl->x_n[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __shared__ int s_item[1];
     __shared__ unsigned long long s_feat[9];
-    if (tid < 9) s_feat[tid] = 0ull;  // ordered before use by the barrier in the loop
+    if (tid < 9) s_feat[tid] = 0ull;  // by wave 0, the only wave that adds to it and reads it
     unsigned long long xcalls = 0;
-    for (;;) {
-        if (tid == 0) s_item[0] = atomicAdd(&ctl->x_head[c], 1);
-        __syncthreads();
-        const int item = s_item[0];
-        __syncthreads();
+    // item w to work-group w, then the queue from G on (as in the marching step)
+    for (int it = 0;; ++it) {
+        int item = w;
+        if (it > 0) {
+            if (G >= nx) break;
+            if (tid == 0) s_item[0] = G + atomicAdd(&ctl->x_head[c], 1);
+            __syncthreads();
+            item = s_item[0];
+            __syncthreads();
+        }
         if (item >= nx) break;
         const int64_t ib = item < kp.nblk ? kp.xlist[item] : -1;
         if ((uint64_t)ib >= (uint64_t)kp.nblk) {
@@ -713,7 +724,7 @@ __global__ void __launch_bounds__(64 * W)
         }
         const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-        march_phase<R, B, W>(kp, r, lbound, smem);
+        march_phase<R, B, W>(kp, r, lbound, smem, G, w);
         grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
         if (read_abort(ctl)) break;
         // list[c] has been consumed: clear its counters for restart r + 1, which appends
@@ -798,7 +809,7 @@ __global__ void __launch_bounds__(64 * W)
 {
     extern __shared__ __align__(16) char smem[];
     if (read_abort(kp.ctl)) return;
-    march_phase<R, B, W>(kp, r, 0.0, smem);
+    march_phase<R, B, W>(kp, r, 0.0, smem, (int)gridDim.x, (int)blockIdx.x);
 }
 
 template <typename R, int B, int W>
