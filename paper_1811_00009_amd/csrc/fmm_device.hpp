@@ -34,11 +34,13 @@ __device__ __forceinline__ bool is_known(uint32_t t) { return t >= kKnownFix; } 
 // Faces: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z; the opposite face is f ^ 1.
 
 // ---------------------------------------------------------------- control block
+constexpr int kBarGroups = 64;  // arrival groups of the grid barrier
+
 struct Ctl {
     // Counters that every work-group touches in each restart sit on 128-byte lines of
     // their own, so the barrier's arrivals, its polled generation, the queue heads and
     // the list appends do not contend for one line.
-    alignas(128) unsigned bar_count;  // grid barrier arrivals
+    alignas(128) unsigned bar_count;  // grid barrier arrivals of the group leaders
     alignas(128) unsigned bar_gen;    // grid barrier generation (polled)
     int abort;                        // first error code raised on the device (0 = none)
     alignas(128) int q_head[2];       // march work-queue heads, by restart parity
@@ -53,6 +55,9 @@ struct Ctl {
                                       // (2^20 fixed point), unused; by parity of the list
     long long restarts;
     double final_bound;
+    struct alignas(128) BarGroup {
+        unsigned count;
+    } bar_grp[kBarGroups];            // grid barrier arrivals, work-group w in group w % 64
 };
 
 // Device-side error codes (stored in Ctl::abort; mapped to fmm.h codes by the host).

@@ -53,6 +53,13 @@ __device__ __forceinline__ double fixed_bound(int64_t r, double stride, double w
 // another work-group has raised an error, it gives up and the caller leaves
 // the restart loop.
 //
+// Arrivals go in two levels, so that no counter takes more than ~G/64 + 64
+// of them: work-group w arrives at the counter of group w % 64, the last of
+// each group (after an acquire, so it carries the group's stores on) arrives
+// at the top counter, and the last of those releases the generation.  Each
+// last arriver resets its counter before passing on; nobody arrives again
+// before the generation moves, which happens after every reset.
+//
 // The wait polls with relaxed agent-scope loads (they read the coherent value
 // without touching the caches) and acquires once after the generation moved:
 // an acquire on every poll would invalidate the XCD's L2 under the work-groups
@@ -65,13 +72,27 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
     if (threadIdx.x == 0) {
         const unsigned gen = __hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED,
                                                __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELEASE,
-                                                     __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == G - 1) {
+        const unsigned w = blockIdx.x, grp = w % kBarGroups;
+        const unsigned ngroups = G < (unsigned)kBarGroups ? G : (unsigned)kBarGroups;
+        const unsigned gsize = (G - 1 - grp) / kBarGroups + 1;  // work-groups of group grp
+        bool released = false;
+        const unsigned pg = __hip_atomic_fetch_add(&ctl->bar_grp[grp].count, 1u, __ATOMIC_RELEASE,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (pg == gsize - 1) {
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+            __hip_atomic_store(&ctl->bar_grp[grp].count, 0u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned prev = __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELEASE,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (prev == ngroups - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ctl->bar_gen, gen + 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+                released = true;
+            }
+        }
+        if (!released) {
             const int64_t t0 = wall_ticks();
             int polls = 0;
             while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
