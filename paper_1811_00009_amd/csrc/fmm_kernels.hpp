@@ -513,6 +513,22 @@ __device__ void append_next(const KParams<R> &kp, int c, int64_t r, int64_t ib, 
     if (kp.nprob > 1) atomicMax(&kp.prob_lastr[kp.blk_prob[ib]], (int)r);
 }
 
+// Counts a work-group gathers over its phases (thread 0's copy), added to the control
+// block once, when the kernel ends.
+struct Totals {
+    unsigned long long pops = 0, march_calls = 0, tile_loads = 0, exchange_calls = 0;
+};
+
+__device__ __forceinline__ void flush_totals(Ctl *ctl, const Totals &t)
+{
+    if (t.march_calls) {
+        atomicAdd(&ctl->pops, t.pops);
+        atomicAdd(&ctl->march_calls, t.march_calls);
+        atomicAdd(&ctl->tile_loads, t.tile_loads);
+    }
+    if (t.exchange_calls) atomicAdd(&ctl->exchange_calls, t.exchange_calls);
+}
+
 // The restart features a work-group gathered in one phase (integer sums, so the order in
 // which work-groups add them does not matter), one atomic per nonzero entry.
 __device__ __forceinline__ void flush_features(Ctl *ctl, int cn, const unsigned long long *lfeat)
@@ -531,7 +547,8 @@ __device__ __forceinline__ void flush_features(Ctl *ctl, int cn, const unsigned 
 // that stays active goes on the next march list right away (an exchange can
 // only activate a block, never deactivate it).
 template <typename R, int B, int W>
-__device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem, int G, int w)
+__device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem, int G, int w,
+                            Totals &tot)
 {
     const int c = (int)(r & 1);
     const int tid = threadIdx.x;
@@ -608,12 +625,10 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         if (tid == 0 && a) append_next<R>(kp, c, r, ib, max(np, nb), nb, s_feat);
     }
     if (tid == 0 && kp.want_features) flush_features(ctl, c ^ 1, s_feat);
-    if (tid == 0 && mcalls) {
-        atomicAdd(&ctl->pops, pops);
-        atomicAdd(&ctl->rpops[c], pops);
-        atomicAdd(&ctl->march_calls, mcalls);
-        atomicAdd(&ctl->tile_loads, loads);
-    }
+    tot.pops += pops;
+    tot.march_calls += mcalls;
+    tot.tile_loads += loads;
+    if (kp.trace && tid == 0 && pops) atomicAdd(&ctl->rpops[c], pops);  // the restart's pops
 }
 
 // Exchanging step of restart r: the blocks whose C flags were raised in this
@@ -622,7 +637,7 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
 // joins the next march list; for a block that was already on it the band-size
 // feature moves to the bin of its new band size.
 template <typename R, int B, int W>
-__device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int G, int w)
+__device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int G, int w, Totals &tot)
 {
     const int c = (int)(r & 1);
     const int tid = threadIdx.x;
@@ -666,7 +681,7 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
         }
     }
     if (tid == 0 && kp.want_features) flush_features(ctl, c ^ 1, s_feat);
-    if (tid == 0 && xcalls) atomicAdd(&ctl->exchange_calls, xcalls);
+    tot.exchange_calls += xcalls;
 }
 
 // ---------------------------------------------------------------- stride network
@@ -725,6 +740,7 @@ __global__ void __launch_bounds__(64 * W)
     if (read_abort(ctl)) return;
     const ProbDesc &p0 = kp.prob[0];
     double prev_bound = 0.0, lstride = p0.stride, lbound = 0.0;
+    Totals tot;
     for (int64_t r = 1;; ++r) {
         const int c = (int)(r & 1);
         if (kp.stride_mode) {
@@ -745,7 +761,7 @@ __global__ void __launch_bounds__(64 * W)
         }
         const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-        march_phase<R, B, W>(kp, r, lbound, smem, G, w);
+        march_phase<R, B, W>(kp, r, lbound, smem, G, w, tot);
         grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
         if (read_abort(ctl)) break;
         // list[c] has been consumed: clear its counters for restart r + 1, which appends
@@ -755,7 +771,7 @@ __global__ void __launch_bounds__(64 * W)
             for (int k = 0; k < 4; ++k) ctl->bin_n[c][k] = 0;
             for (int k = 0; k < 10; ++k) ctl->feat[c][k] = 0;
         }
-        exchange_phase<R, B, W>(kp, r, smem, G, w);
+        exchange_phase<R, B, W>(kp, r, smem, G, w, tot);
         grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
         if (read_abort(ctl)) break;
         const int nnext = __hip_atomic_load(&ctl->n_list[c ^ 1], __ATOMIC_RELAXED,
@@ -806,6 +822,7 @@ __global__ void __launch_bounds__(64 * W)
             prev_bound = bound_r;
         }
     }
+    if (tid == 0) flush_totals(ctl, tot);
 }
 
 // ---------------------------------------------------------------- host-driven loop
@@ -830,7 +847,9 @@ __global__ void __launch_bounds__(64 * W)
 {
     extern __shared__ __align__(16) char smem[];
     if (read_abort(kp.ctl)) return;
-    march_phase<R, B, W>(kp, r, 0.0, smem, (int)gridDim.x, (int)blockIdx.x);
+    Totals tot;
+    march_phase<R, B, W>(kp, r, 0.0, smem, (int)gridDim.x, (int)blockIdx.x, tot);
+    if (threadIdx.x == 0) flush_totals(kp.ctl, tot);
 }
 
 template <typename R, int B, int W>
@@ -838,7 +857,9 @@ __global__ void __launch_bounds__(64 * W) k_exchange(KParams<R> kp, int64_t r)
 {
     extern __shared__ __align__(16) char smem[];
     if (read_abort(kp.ctl)) return;
-    exchange_phase<R, B, W>(kp, r, smem, (int)gridDim.x, (int)blockIdx.x);
+    Totals tot;
+    exchange_phase<R, B, W>(kp, r, smem, (int)gridDim.x, (int)blockIdx.x, tot);
+    if (threadIdx.x == 0) flush_totals(kp.ctl, tot);
 }
 
 // ---------------------------------------------------------------- Alg. 1 and layout
