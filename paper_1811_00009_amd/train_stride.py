@@ -20,6 +20,11 @@
 Writes <out>/stride_mlp_b<B>.f32 (the device blob: 1505 parameters, 12 feature
 means, 12 feature standard deviations, little-endian FP32) and
 <out>/stride_mlp_b<B>.json (data, training and evaluation record).
+
+    python -m paper_1811_00009_amd.train_stride --eval-only
+
+evaluates the blob already in <out> (step 4 only) and writes
+<out>/stride_mlp_b<B>.eval.json.
 """
 from __future__ import annotations
 
@@ -116,6 +121,24 @@ def evaluate(fmm, stride, torch, blob_dev, seeds, n, block):
             "Mpts_per_s_best_fixed": pts / (tot[best_m] / 1e3) / 1e6}
 
 
+def run_evals(fmm, stride, torch, blob_dev, args):
+    """Step 4: held-out coarse-cell fields at eval_n^3, unseen fields of the other
+    families at n^3."""
+    evals = {"coarse_cells_held_out": evaluate(
+        fmm, stride, torch, blob_dev, [[50, s] for s in range(args.eval_fields)], args.eval_n,
+        args.block)}
+    # unseen fields of the other families (seeds beyond the training range)
+    for name, fam in (("fourier_unseen", 6), ("sine_unseen", 7)):
+        evals[name] = evaluate(fmm, stride, torch, blob_dev,
+                               [[fam, 1000 + s] for s in range(args.other_eval_fields)],
+                               args.n, args.block)
+    for name, ev in evals.items():
+        log(f"{name}: learned {ev['Mpts_per_s_learned']:.1f} Mpts/s, fixed 2h "
+            f"{ev['Mpts_per_s_fixed_2h']:.1f}, best fixed (m={ev['best_fixed_multiplier']}) "
+            f"{ev['Mpts_per_s_best_fixed']:.1f}")
+    return evals
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--fields", type=int, default=60, help="coarse-cell training fields")
@@ -131,6 +154,8 @@ def main(argv=None):
     ap.add_argument("--other-eval-fields", type=int, default=2)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "weights"))
+    ap.add_argument("--eval-only", action="store_true",
+                    help="evaluate the blob already in --out instead of training one")
     args = ap.parse_args(argv)
 
     import torch
@@ -138,6 +163,15 @@ def main(argv=None):
     fmm.load()
     if not torch.cuda.is_available():
         raise SystemExit("train_stride needs a GPU")
+    if args.eval_only:
+        path = os.path.join(args.out, f"stride_mlp_b{args.block}.f32")
+        blob = np.fromfile(path, dtype="<f4")
+        if blob.size != 1505 + 24 or not np.all(np.isfinite(blob)):
+            raise SystemExit(f"{path}: not a stride network blob")
+        evals = run_evals(fmm, stride, torch, torch.from_numpy(blob).cuda(), args)
+        with open(os.path.join(args.out, f"stride_mlp_b{args.block}.eval.json"), "w") as f:
+            json.dump({"blob": os.path.basename(path), "eval": evals}, f, indent=1)
+        return
     t0 = time.perf_counter()
     plan = [(5, args.fields), (6, args.fourier_fields), (7, args.sine_fields)]
     X, y, best = collect(fmm, stride, torch, plan, args.n, args.block, args.rule)
@@ -153,18 +187,7 @@ def main(argv=None):
     path = os.path.join(args.out, f"stride_mlp_b{args.block}.f32")
     blob.astype("<f4").tofile(path)
     blob_dev = torch.from_numpy(blob.astype(np.float32)).cuda()
-    evals = {"coarse_cells_held_out": evaluate(
-        fmm, stride, torch, blob_dev, [[50, s] for s in range(args.eval_fields)], args.eval_n,
-        args.block)}
-    # unseen fields of the other families (seeds beyond the training range)
-    for name, fam in (("fourier_unseen", 6), ("sine_unseen", 7)):
-        evals[name] = evaluate(fmm, stride, torch, blob_dev,
-                               [[fam, 1000 + s] for s in range(args.other_eval_fields)],
-                               args.n, args.block)
-    for name, ev in evals.items():
-        log(f"{name}: learned {ev['Mpts_per_s_learned']:.1f} Mpts/s, fixed 2h "
-            f"{ev['Mpts_per_s_fixed_2h']:.1f}, best fixed (m={ev['best_fixed_multiplier']}) "
-            f"{ev['Mpts_per_s_best_fixed']:.1f}")
+    evals = run_evals(fmm, stride, torch, blob_dev, args)
     rec = {"blob": os.path.basename(path), "layout": "1505 params (W1 32x12, b1, W2 32x32, b2, "
            "W3 1x32, b3), 12 feature means, 12 feature stds; FP32 little-endian",
            "train": {"fields": {"coarse_cells (5, s)": args.fields,
