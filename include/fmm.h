@@ -182,7 +182,11 @@ typedef struct {
  * sample problems, once each after one warm-up.  Results are cached in memory
  * and, when cache_path is not NULL, in a small text file keyed by device name,
  * dtype and a size bin, so a later call with the same key does not time again.
- * psi_dev of the sample problems is overwritten.
+ * psi_dev of the sample problems is overwritten.  The sample should carry about
+ * as much work per restart as the batch it stands for: with too little, the grid
+ * barrier dominates the timing and favours fewer, larger work-groups (8 of 512
+ * uneven grids picked two waves per block, 32 pick one, which runs the whole
+ * batch 2.2x faster).
  */
 int fmm_autotune(int32_t nsamples, const fmm_problem *samples, int32_t dtype,
                  const char *cache_path, void *hip_stream, fmm_tuning *out);
