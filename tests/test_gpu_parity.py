@@ -150,6 +150,20 @@ def test_launch_modes_and_waves_are_bitwise_equal(fmm_lib, launch, waves):
     assert st["restarts"] == rs["restarts"] and st["pops"] == rs["pops"]
 
 
+def test_grid_sizes_around_the_barrier_groups(fmm_lib):
+    """Persistent grids of every shape the two-level grid barrier meets (fewer work-groups
+    than its 64 arrival groups, more, not a multiple of 64) and work queues longer or
+    shorter than the grid: the same psi and counts bitwise."""
+    p = inputs.random_problem(321, shape=(64, 64, 48), nsrc=3, dtype=np.float32, obstacles=0.01)
+    ref, sr = _run(fmm_lib, p, np.float32, block=8)
+    for g in (65, 100, 127, 130, 200, 257):
+        got, st = _run(fmm_lib, p, np.float32, block=8, grid_limit=g)
+        assert st["grid"] == g
+        assert np.array_equal(got, ref), g
+        for k in ("restarts", "pops", "march_calls", "exchange_calls"):
+            assert st[k] == sr[k], (g, k)
+
+
 def test_run_to_run_and_grid_size_determinism(fmm_lib):
     p = inputs.random_problem(320, shape=(32, 32, 32), nsrc=2, dtype=np.float32)
     a, _ = _run(fmm_lib, p, np.float32, block=8)
