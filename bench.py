@@ -353,8 +353,8 @@ def cpu_baseline_batched(seconds_target=12.0):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; --gpus must be 1 "
-              "(the multi-GPU sharding of the block grid is a design, not part of this build)",
+        print("bench.py: the solver runs on one GPU; --gpus must be 1 "
+              "(sharding the block grid over several GPUs is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
