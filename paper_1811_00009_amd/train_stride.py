@@ -56,14 +56,14 @@ def field(seed_words, n, torch):
     return p, p.F
 
 
-def collect(fmm, stride, torch, plan, n, block, rule):
-    """plan: [(family seed word, count)]."""
+def collect(fmm, stride, torch, plan, n, block, rule, mults):
+    """plan: [(family seed word, count)]; mults: the fixed multipliers traced."""
     Xs, ys, best, t0, k = [], [], [], time.perf_counter(), 0
     for fam, count in plan:
         for s in range(count):
             p, F = field([fam, s], n, torch)
             traces = {}
-            for m in stride.MULTIPLIERS:
+            for m in mults:
                 _, st, rows = stride.trace_solve(fmm, F, p.h, p.sources, block=block,
                                                  multiplier=m)
                 traces[m] = rows
@@ -80,16 +80,18 @@ def collect(fmm, stride, torch, plan, n, block, rule):
     return np.concatenate(Xs), np.concatenate(ys), best
 
 
-def evaluate(fmm, stride, torch, blob_dev, seeds, n, block):
-    """Device time of every fixed multiplier and of the learned stride on the held-out
-    fields `seeds` (seed words); psi of the learned solve against the fixed 2h solve."""
+def evaluate(fmm, stride, torch, blob_dev, seeds, n, block, mults=None):
+    """Device time of every fixed multiplier (mults, default stride.MULTIPLIERS; 1.0, the
+    fixed 2h, among them) and of the learned stride on the held-out fields `seeds` (seed
+    words); psi of the learned solve against the fixed 2h solve."""
+    mults = tuple(mults or stride.MULTIPLIERS)
     res = []
     for sw in seeds:
         p, F = field(sw, n, torch)
         out = torch.empty_like(F)
         row = {"seed": list(sw), "source": list(p.sources[0][:3]), "fixed_ms": {}}
         fmm.solve(F, p.h, p.sources, block=block, out=out)  # warm-up
-        for m in stride.MULTIPLIERS:
+        for m in mults:
             _, st = fmm.solve(F, p.h, p.sources, block=block, stride=m * 2 * p.h, out=out,
                               with_stats=True)
             row["fixed_ms"][str(m)] = st["elapsed_ms"]
@@ -108,7 +110,7 @@ def evaluate(fmm, stride, torch, blob_dev, seeds, n, block):
         log(f"eval field {sw} at {n}^3: fixed {row['fixed_ms']} learned "
             f"{row['learned_ms']:.1f} ms")
         del F, out, ref
-    tot = {m: sum(r["fixed_ms"][str(m)] for r in res) for m in stride.MULTIPLIERS}
+    tot = {m: sum(r["fixed_ms"][str(m)] for r in res) for m in mults}
     best_m = min(tot, key=tot.get)
     learned = sum(r["learned_ms"] for r in res)
     pts = len(res) * n ** 3
@@ -126,12 +128,12 @@ def run_evals(fmm, stride, torch, blob_dev, args):
     families at n^3."""
     evals = {"coarse_cells_held_out": evaluate(
         fmm, stride, torch, blob_dev, [[50, s] for s in range(args.eval_fields)], args.eval_n,
-        args.block)}
+        args.block, args.multipliers)}
     # unseen fields of the other families (seeds beyond the training range)
     for name, fam in (("fourier_unseen", 6), ("sine_unseen", 7)):
         evals[name] = evaluate(fmm, stride, torch, blob_dev,
                                [[fam, 1000 + s] for s in range(args.other_eval_fields)],
-                               args.n, args.block)
+                               args.n, args.block, args.multipliers)
     for name, ev in evals.items():
         log(f"{name}: learned {ev['Mpts_per_s_learned']:.1f} Mpts/s, fixed 2h "
             f"{ev['Mpts_per_s_fixed_2h']:.1f}, best fixed (m={ev['best_fixed_multiplier']}) "
@@ -156,10 +158,17 @@ def main(argv=None):
                                                   "weights"))
     ap.add_argument("--eval-only", action="store_true",
                     help="evaluate the blob already in --out instead of training one")
+    ap.add_argument("--multipliers", default=None,
+                    help="comma-separated fixed multipliers to trace and compare (1.0 among "
+                         "them); default: stride.MULTIPLIERS")
     args = ap.parse_args(argv)
 
     import torch
     from . import fmm, stride
+    args.multipliers = (tuple(float(m) for m in args.multipliers.split(","))
+                        if args.multipliers else tuple(stride.MULTIPLIERS))
+    if 1.0 not in args.multipliers:
+        raise SystemExit("--multipliers must include 1.0 (the fixed 2h)")
     fmm.load()
     if not torch.cuda.is_available():
         raise SystemExit("train_stride needs a GPU")
@@ -174,7 +183,8 @@ def main(argv=None):
         return
     t0 = time.perf_counter()
     plan = [(5, args.fields), (6, args.fourier_fields), (7, args.sine_fields)]
-    X, y, best = collect(fmm, stride, torch, plan, args.n, args.block, args.rule)
+    X, y, best = collect(fmm, stride, torch, plan, args.n, args.block, args.rule,
+                         args.multipliers)
     hist = {}
     for fam, _, m in best:
         hist.setdefault(fam, {}).setdefault(m, 0)
@@ -194,7 +204,7 @@ def main(argv=None):
                                 "fourier (6, s)": args.fourier_fields,
                                 "sine (7, s)": args.sine_fields},
                      "n": args.n, "rule": args.rule, "fastest_multiplier_per_family": hist,
-                     "block": args.block, "multipliers": list(stride.MULTIPLIERS),
+                     "block": args.block, "multipliers": list(args.multipliers),
                      "samples": int(len(y)), "steps": args.steps, "lr": args.lr,
                      "loss_first": float(lh[0]), "loss_last": float(lh[-1])},
            "eval": evals}
