@@ -8,6 +8,7 @@ multiply-adds, as on the device with its FP32 denormals on) and compares every r
 bit for bit with x / 3.  The rounding is odd-symmetric, so negative inputs follow.
 """
 import os
+import platform
 import shutil
 import subprocess
 
@@ -37,7 +38,8 @@ int main(void) {
 """
 
 
-@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs gcc")
+@pytest.mark.skipif(shutil.which("gcc") is None or platform.machine() not in ("x86_64", "AMD64"),
+                    reason="needs gcc on x86-64 (-mfma)")
 def test_div3_is_the_ieee_quotient_for_all_binary32(tmp_path):
     src = tmp_path / "div3.c"
     exe = tmp_path / "div3"
