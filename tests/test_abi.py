@@ -110,3 +110,18 @@ def test_batched_and_mlp_reject_bad_arguments():
     assert lib.fmm_mlp_forward(None, None, 0, None, None) == fmm.FMM_EINVAL
     assert lib.fmm_mlp_adam(None, None, None, None, 0.1, 0.9, 0.99, 1e-8, 0, None) == fmm.FMM_EINVAL
     assert lib.fmm_autotune(0, None, 0, None, None, None) == fmm.FMM_EINVAL
+
+
+def test_locate_min_probe_rejects_bad_arguments_on_the_host():
+    lib = fmm.load()
+    buf = C.create_string_buffer(64)  # never dereferenced: every case fails before device work
+    p, b, v, i = (C.cast(buf, C.c_void_p),) * 4
+    call = lib.fmm_selftest_band_argmin
+    assert call(fmm.FMM_F32, 16, None, b, 1, 0, v, i, None) == fmm.FMM_EINVAL   # null psi
+    assert call(fmm.FMM_F32, 16, p, None, 1, 0, v, i, None) == fmm.FMM_EINVAL   # null band
+    assert call(fmm.FMM_F32, 16, p, b, 1, 100, v, i, None) == fmm.FMM_EINVAL    # cap % 512
+    assert call(fmm.FMM_F32, 16, p, b, 1, -512, v, i, None) == fmm.FMM_EINVAL
+    assert call(7, 16, p, b, 1, 0, v, i, None) == fmm.FMM_EINVAL                # dtype
+    assert call(fmm.FMM_F32, 12, p, b, 1, 0, v, i, None) == fmm.FMM_EINVAL      # block size
+    assert call(fmm.FMM_F32, 16, p, b, 0, 0, v, i, None) == fmm.FMM_EINVAL      # empty band
+    assert call(fmm.FMM_F64, 8, p, b, 1000, 0, v, i, None) == fmm.FMM_EINVAL    # n >= (B+2)^3
