@@ -203,28 +203,32 @@ def _load_par():
         from . import build as _b
         _b.build()
     lib = C.CDLL(path)
-    f = lib.cpu_block_fmm_par_f64
-    f.restype = C.c_int
-    f.argtypes = [_i64, _i64, _i64, _dbl, _vp, _i32, _vp, _vp, _i32, _dbl, _dbl, _i32, _i64,
-                  _vp, _vp, _vp, _vp]
+    for sfx in ("f64", "f32"):
+        f = getattr(lib, f"cpu_block_fmm_par_{sfx}")
+        f.restype = C.c_int
+        f.argtypes = [_i64, _i64, _i64, _dbl, _vp, _i32, _vp, _vp, _i32, _dbl, _dbl, _i32, _i64,
+                      _vp, _vp, _vp, _vp]
     _par = lib
     return lib
 
 
 def block_fmm_parallel(F: np.ndarray, h: float, sources, block: int, stride: float,
-                       width: float = math.inf, threads: int = 0, stats: bool = False):
+                       width: float = math.inf, threads: int = 0, dtype=np.float64,
+                       stats: bool = False):
     """The paper's parallel CPU solver (Sec. 2.7): the block method of block_fmm with
-    each step's blocks spread over OpenMP threads; FP64.  A comparison baseline."""
+    each step's blocks spread over OpenMP threads, in FP64 or FP32 (bitwise the block
+    reference of the same precision).  A comparison baseline, and the reference for
+    grids too large for the sequential block reference."""
     lib = _load_par()
-    F = _speed(F, np.float64)
+    F = _speed(F, dtype)
     nz, ny, nx = F.shape
-    idx, val = _sources(F.shape, sources, np.float64)
+    idx, val = _sources(F.shape, sources, dtype)
     psi = np.empty_like(F)
     r, pops, used = _i64(0), _i64(0), _i32(0)
-    rc = lib.cpu_block_fmm_par_f64(nx, ny, nz, h, _ptr(F), len(idx), _ptr(idx), _ptr(val), block,
-                                   stride, width, threads, 0, _ptr(psi), C.byref(r), C.byref(pops),
-                                   C.byref(used))
-    _check(rc, "cpu_block_fmm_par_f64")
+    fn = lib.cpu_block_fmm_par_f64 if dtype == np.float64 else lib.cpu_block_fmm_par_f32
+    rc = fn(nx, ny, nz, h, _ptr(F), len(idx), _ptr(idx), _ptr(val), block, stride, width,
+            threads, 0, _ptr(psi), C.byref(r), C.byref(pops), C.byref(used))
+    _check(rc, "cpu_block_fmm_par")
     if stats:
         return psi, {"restarts": r.value, "pops": pops.value, "threads": used.value}
     return psi

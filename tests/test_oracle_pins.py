@@ -258,9 +258,14 @@ def test_shifted_root_matches_literal_coefficients():
     a = oracle.fmm(p.F, p.h, p.sources)
     b = oracle.fmm(p.F, p.h, p.sources, literal=True)
     assert np.max(np.abs(a - b)) <= 1e-12
-    # and in FP32 the literal coefficients lose accuracy the shifted form keeps
+    # and in FP32 the literal coefficients lose accuracy the shifted form keeps: b^2 - a c
+    # cancels when the candidates are close, the shifted discriminant does not
     a32 = oracle.fmm(p.F, p.h, p.sources, dtype=np.float32)
-    assert np.max(np.abs(a32 - a)) <= 1e-5 * np.max(a)
+    l32 = oracle.fmm(p.F, p.h, p.sources, dtype=np.float32, literal=True)
+    e_shift = np.max(np.abs(a32 - a))
+    e_lit = np.max(np.abs(l32 - a))
+    assert e_shift <= 1e-5 * np.max(a)
+    assert e_lit >= 10 * e_shift, (e_lit, e_shift)
 
 
 # ----------------------------------------------------------------------- block method (Alg. 6)
@@ -357,6 +362,60 @@ def test_mlp_gradient_finite_differences():
     assert loss == pytest.approx(np.mean((y - T) ** 2), rel=1e-12)
 
 
+def _mlp_forward_numpy(P, X):
+    """The 12-32-32-1 network written out with numpy matrix products, independent of
+    the oracle's loops: unpack W1 (32x12), b1, W2 (32x32), b2, w3 (32), b3 row-major,
+    two ReLU layers, then log m = ln(1/4) + sigmoid(z) * (ln 8 - ln(1/4))."""
+    o = 0
+    W1 = P[o:o + 32 * 12].reshape(32, 12); o += 32 * 12
+    b1 = P[o:o + 32]; o += 32
+    W2 = P[o:o + 32 * 32].reshape(32, 32); o += 32 * 32
+    b2 = P[o:o + 32]; o += 32
+    w3 = P[o:o + 32]; o += 32
+    b3 = P[o]; o += 1
+    assert o == P.size
+    H1 = np.maximum(X @ W1.T + b1, 0.0)
+    H2 = np.maximum(H1 @ W2.T + b2, 0.0)
+    z = H2 @ w3 + b3
+    sig = 1.0 / (1.0 + np.exp(-z))
+    lo, hi = math.log(0.25), math.log(8.0)
+    return lo + (hi - lo) * sig
+
+
+def test_mlp_forward_matches_independent_numpy_network():
+    """Pin of the FP64 forward pass against the same network stated with numpy matrix
+    products: a transposed weight layout, a missing ReLU or a wrong output span fails."""
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        P = rng.normal(0, 0.5, size=oracle.MLP_NPARAMS)
+        X = rng.normal(0, 1.5, size=(257, 12))
+        got = oracle.mlp_forward(P, X)
+        ref = _mlp_forward_numpy(P, X)
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    # both ends of the output span are reached and never crossed
+    P = np.zeros(oracle.MLP_NPARAMS)
+    P[-1] = 60.0
+    assert oracle.mlp_forward(P, np.zeros((1, 12)))[0] == pytest.approx(math.log(8.0), abs=1e-12)
+    P[-1] = -60.0
+    assert oracle.mlp_forward(P, np.zeros((1, 12)))[0] == pytest.approx(math.log(0.25), abs=1e-12)
+    # a layout check the loops cannot share with numpy by accident: a single nonzero
+    # first-layer weight W1[o][i] routes input i through hidden unit o only
+    P = np.zeros(oracle.MLP_NPARAMS)
+    o_, i_ = 5, 9
+    P[o_ * 12 + i_] = 1.0                      # W1[5][9]
+    P[32 * 12 + 32 + 7 * 32 + o_] = 1.0        # W2[7][5]
+    P[32 * 12 + 32 + 32 * 32 + 32 + 7] = 1.0   # w3[7]
+    X = np.zeros((3, 12))
+    X[0, i_] = 2.0      # passes both ReLUs: z = 2
+    X[1, i_] = -2.0     # cut by the first ReLU: z = 0
+    X[2, 8] = 2.0       # another input: z = 0
+    y = oracle.mlp_forward(P, X)
+    lo, span = math.log(0.25), math.log(32.0)
+    assert y[0] == pytest.approx(lo + span / (1 + math.exp(-2.0)), abs=1e-12)
+    assert y[1] == pytest.approx(lo + span / 2, abs=1e-12)
+    assert y[2] == pytest.approx(lo + span / 2, abs=1e-12)
+
+
 def test_adam_step_matches_closed_form_first_step():
     """First Adam step moves each parameter by lr * sign(g) (bias-corrected moments)."""
     P = np.array([1.0, -2.0, 0.5])
@@ -441,15 +500,19 @@ def test_box_restriction_is_exact_below_boundary_layer_minimum(seed):
 
 
 # ------------------------------------------------------------------ parallel CPU baseline
-@pytest.mark.parametrize("seed,block,stride_h,threads", [(70, 8, 2.0, 4), (71, 4, 0.5, 3),
-                                                         (72, 8, math.inf, 8)])
-def test_parallel_cpu_block_method_equals_block_reference(seed, block, stride_h, threads):
+@pytest.mark.parametrize("seed,block,stride_h,threads,dtype", [
+    (70, 8, 2.0, 4, np.float64), (71, 4, 0.5, 3, np.float64), (72, 8, math.inf, 8, np.float64),
+    (73, 16, 2.0, 5, np.float32), (74, 8, 0.5, 8, np.float32), (75, 4, 3.5, 2, np.float32)])
+def test_parallel_cpu_block_method_equals_block_reference(seed, block, stride_h, threads, dtype):
     """The OpenMP block solver (the paper's parallel version) gives bitwise the sequential
-    block reference's psi, restarts and pops for any thread count (Sec. 2.7)."""
-    p = inputs.random_problem(seed, shape=(32, 24, 40), nsrc=3, obstacles=0.02)
-    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=block, stride=stride_h * p.h, stats=True)
+    block reference's psi, restarts and pops for any thread count (Sec. 2.7), in both
+    precisions."""
+    p = inputs.random_problem(seed, shape=(32, 48, 32), nsrc=3, obstacles=0.02, dtype=dtype)
+    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=block, stride=stride_h * p.h,
+                               dtype=dtype, stats=True)
     got, st = oracle.block_fmm_parallel(p.F, p.h, p.sources, block=block, stride=stride_h * p.h,
-                                        threads=threads, stats=True)
+                                        threads=threads, dtype=dtype, stats=True)
+    assert got.dtype == dtype
     assert np.array_equal(got, ref)
     assert st["restarts"] == rs["restarts"] and st["pops"] == rs["pops"]
     assert st["threads"] == threads
