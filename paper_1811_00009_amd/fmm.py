@@ -161,6 +161,13 @@ def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_pe
     o.width = float(width)
     o.stride_mode = STRIDE_LEARNED if stride_mode == "learned" else STRIDE_FIXED
     if mlp_weights is not None:
+        import torch
+        # the device reads MLP_BLOB_FLOATS float32 values through this pointer
+        if mlp_weights.dtype != torch.float32:
+            raise ValueError("mlp_weights must be a float32 tensor")
+        if mlp_weights.numel() < MLP_BLOB_FLOATS:
+            raise ValueError(f"mlp_weights must hold at least {MLP_BLOB_FLOATS} values "
+                             "(parameters, feature means, feature standard deviations)")
         _check_tensor(mlp_weights, "mlp_weights")
         o.mlp_weights = mlp_weights.data_ptr()
     o.waves_per_block = int(waves_per_block)
@@ -205,15 +212,27 @@ def solve_batched(problems: Sequence, block: int = 16, with_stats: bool = False,
     import torch
     lib = load()
     n = len(problems)
+    if n == 0:
+        raise ValueError("solve_batched needs at least one problem")
     arr = (Problem * n)()
     keep = []
     if outs is None:
         outs = [torch.empty_like(p[0]) for p in problems]
+    elif len(outs) != n:
+        raise ValueError(f"outs holds {len(outs)} tensors for {n} problems")
+    for q, p in enumerate(problems):
+        F = p[0]
+        if F.dim() != 3:
+            raise ValueError(f"F[{q}] must have shape (nz, ny, nx)")
+        # the library writes nx * ny * nz values of F's dtype through outs[q]
+        if outs[q].shape != F.shape or outs[q].dtype != F.dtype:
+            raise ValueError(f"outs[{q}] must match F[{q}] in shape and dtype")
     dtype = None
     for q, p in enumerate(problems):
         F, h, sources = p[0], p[1], p[2]
         stride = float(p[3]) if len(p) > 3 and p[3] is not None else 2.0 * h
         _check_tensor(F, f"F[{q}]")
+        _check_tensor(outs[q], f"outs[{q}]")
         d = _dtype_code(F)
         if dtype is None:
             dtype = d
@@ -247,7 +266,13 @@ def autotune(samples: Sequence, cache_path: Optional[str] = None):
     for q, p in enumerate(samples):
         F, h, sources = p[0], p[1], p[2]
         stride = float(p[3]) if len(p) > 3 and p[3] is not None else 2.0 * h
-        dtype = _dtype_code(F)
+        if F.dim() != 3:
+            raise ValueError(f"samples[{q}]: F must have shape (nz, ny, nx)")
+        _check_tensor(F, f"samples[{q}] F")
+        d = _dtype_code(F)
+        if dtype is not None and d != dtype:
+            raise ValueError("all autotune samples must share the dtype")
+        dtype = d
         nz, ny, nx = F.shape
         src = _sources(sources)
         o = torch.empty_like(F)

@@ -125,3 +125,27 @@ def test_locate_min_probe_rejects_bad_arguments_on_the_host():
     assert call(fmm.FMM_F32, 12, p, b, 1, 0, v, i, None) == fmm.FMM_EINVAL      # block size
     assert call(fmm.FMM_F32, 16, p, b, 0, 0, v, i, None) == fmm.FMM_EINVAL      # empty band
     assert call(fmm.FMM_F64, 8, p, b, 1000, 0, v, i, None) == fmm.FMM_EINVAL    # n >= (B+2)^3
+
+
+def test_binding_checks_batched_outputs_and_weights_on_the_host():
+    """The binding refuses buffers the library would write or read past: outs of the wrong
+    count, shape or dtype, speed fields that are not 3-D, and stride weights that are not
+    float32 or hold fewer values than the device reads.  CPU tensors suffice: every check
+    fires before a pointer is passed."""
+    import torch
+    F = torch.ones(16, 16, 16, dtype=torch.float32)
+    batch = [(F, 0.1, [(1, 1, 1)]), (F, 0.1, [(2, 2, 2)])]
+    with pytest.raises(ValueError, match="outs holds"):
+        fmm.solve_batched(batch, block=8, outs=[torch.empty_like(F)])
+    with pytest.raises(ValueError, match="shape and dtype"):
+        fmm.solve_batched(batch, block=8, outs=[torch.empty_like(F), torch.empty(8, 16, 16)])
+    with pytest.raises(ValueError, match="shape and dtype"):
+        fmm.solve_batched(batch, block=8, outs=[torch.empty_like(F), torch.empty_like(F).double()])
+    with pytest.raises(ValueError, match=r"shape \(nz, ny, nx\)"):
+        fmm.solve_batched([(F.reshape(16, 256), 0.1, [(1, 1, 1)])], block=8)
+    with pytest.raises(ValueError, match="at least one"):
+        fmm.solve_batched([], block=8)
+    with pytest.raises(ValueError, match="float32"):
+        fmm.make_options(mlp_weights=torch.zeros(fmm.MLP_BLOB_FLOATS, dtype=torch.float64))
+    with pytest.raises(ValueError, match="at least"):
+        fmm.make_options(mlp_weights=torch.zeros(fmm.MLP_NPARAMS, dtype=torch.float32))
