@@ -11,24 +11,30 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmm_hip.so")
-SOURCES = ["fmm_host.hip", "fmm_mlp.hip", "fmm_tune.hip"]
+SOURCES = ["fmm_host.hip", "fmm_mlp.hip"]
 ARCH = os.environ.get("FMM_OFFLOAD_ARCH", "gfx950")
 
 
-def build(verbose: bool = False) -> str:
+# The profiling build: the same sources with the per-segment cycle account compiled in
+# (timestamps at each segment boundary of a pop, read back by fmm_cycle_account).
+CYCLES_LIB = os.path.join(HERE, "libfmm_hip_cycles.so")
+
+
+def build(verbose: bool = False, cycles: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    lib = CYCLES_LIB if cycles else LIB
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
            "-I", os.path.join(os.path.dirname(HERE), "include"),
-           "-o", LIB + ".tmp"] + srcs
+           "-o", lib + ".tmp"] + (["-DFMM_CYCLES"] if cycles else []) + srcs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, cycles="--cycles" in sys.argv)

@@ -33,6 +33,87 @@ __device__ __forceinline__ bool is_known(uint32_t t) { return t >= kKnownFix; } 
 
 // Faces: 0 -x, 1 +x, 2 -y, 3 +y, 4 -z, 5 +z; the opposite face is f ^ 1.
 
+// ---------------------------------------------------------------- cycle account
+// Profiling build only (-DFMM_CYCLES, libfmm_hip_cycles.so): the march of every block
+// takes a shader-clock timestamp at each segment boundary of a pop, after waiting for
+// every memory and LDS operation in flight, and adds the segment's cycles to its
+// work-group's row of fmm_cyc_rows.  The waits serialise what the normal build
+// overlaps, so the segments add up to more than a pop costs without them; both totals
+// are reported.  In the normal build every mark compiles to nothing.
+#ifdef FMM_CYCLES
+constexpr int kCycSegs = 16;
+constexpr int kCycRows = 8192;
+__device__ unsigned long long fmm_cyc_rows[kCycRows][kCycSegs];
+struct Cyc {
+    unsigned long long t = 0, tl = 0;
+    unsigned long long acc[kCycSegs] = {};
+    // waits for LDS and scalar loads only (vmcnt and expcnt left at their maximum)
+    __device__ static __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+    __device__ static __forceinline__ void wait_all() { __builtin_amdgcn_s_waitcnt(0); }
+    __device__ __forceinline__ void start()
+    {
+        wait_all();
+        t = __builtin_amdgcn_s_memtime();
+    }
+    // segment k ends here (wave-uniform code only); full = also wait for device memory
+    __device__ __forceinline__ void mark(int k, bool full = false)
+    {
+        if (full) wait_all();
+        else wait_lds();
+        const unsigned long long n = __builtin_amdgcn_s_memtime();
+        acc[k] += n - t;
+        t = n;
+    }
+    // sub-segments inside a lane-divergent region: kept per lane (lane 0's are flushed)
+    __device__ __forceinline__ void lstart()
+    {
+        wait_lds();
+        tl = __builtin_amdgcn_s_memtime();
+    }
+    __device__ __forceinline__ void lmark(int k, bool full = false)
+    {
+        if (full) wait_all();
+        else wait_lds();
+        const unsigned long long n = __builtin_amdgcn_s_memtime();
+        acc[k] += n - tl;
+        tl = n;
+    }
+    __device__ __forceinline__ void count(int k, unsigned long long v) { acc[k] += v; }
+    __device__ __forceinline__ void flush()
+    {
+        if (threadIdx.x == 0 && blockIdx.x < (unsigned)kCycRows)
+            for (int k = 0; k < kCycSegs; ++k) fmm_cyc_rows[blockIdx.x][k] += acc[k];
+    }
+};
+#define FMM_CYC_PARAM , Cyc &cyc
+#define FMM_CYC_ARG , cyc
+#define FMM_CYC_DECL Cyc cyc
+#define FMM_CYC_START() cyc.start()
+#define FMM_CYC(k) cyc.mark(k)
+#define FMM_CYC_FULL(k) cyc.mark(k, true)
+#define FMM_CYC_LSTART() cyc.lstart()
+#define FMM_CYC_L(k) cyc.lmark(k)
+#define FMM_CYC_LFULL(k) cyc.lmark(k, true)
+#define FMM_CYC_COUNT(k, v) cyc.count(k, v)
+#else
+#define FMM_CYC_PARAM
+#define FMM_CYC_ARG
+#define FMM_CYC_DECL
+#define FMM_CYC_START() ((void)0)
+#define FMM_CYC(k) ((void)0)
+#define FMM_CYC_FULL(k) ((void)0)
+#define FMM_CYC_LSTART() ((void)0)
+#define FMM_CYC_L(k) ((void)0)
+#define FMM_CYC_LFULL(k) ((void)0)
+#define FMM_CYC_COUNT(k, v) ((void)0)
+#endif
+// Segments of the account (wave-uniform, in order): 0 band read, 1 psi gather and
+// per-lane minimum, 2 cross-lane minimum and key, 3 bound test, neighbour tag and psi
+// reads and Remove_Min, 4 the six neighbour solves, 5 insert and loop back; per march:
+// 6 tile load, 7 face test, tile store and flags.  Inside the solves, lane 0's own
+// solves (the -x neighbour): 8 stencil reads, 9 wait for h^2/F^2, 10 quadratic root and
+// write; 11 counts them.  Counters: 12 pops, 13 marches.
+
 // ---------------------------------------------------------------- control block
 constexpr int kBarGroups = 64;  // arrival groups of the grid barrier
 
@@ -268,7 +349,7 @@ __device__ __forceinline__ bool val_eq(double a, double b) { return a == b; }
 template <typename R>
 __device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, const uint16_t *g_band,
                                                int cap, const FMM_LDS R *s_psi, int n, int c0,
-                                               int lane, R &m_out, uint32_t &k_out)
+                                               int lane, R &m_out, uint32_t &k_out FMM_CYC_PARAM)
 {
     const int base = c0 + lane * 8;
     v4u raw;
@@ -284,6 +365,7 @@ __device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, c
         raw.w = __builtin_nontemporal_load(g + 3);
     }
     const uint32_t w4[4] = {raw.x, raw.y, raw.z, raw.w};
+    FMM_CYC(0);
     uint32_t ids[8];
     R vs[8];
 #pragma unroll
@@ -313,7 +395,7 @@ __device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, c
 // held in LDS (S = 1, 2 or 4): the narrow form of band_chunk_min for small bands.
 template <typename R, int S>
 __device__ __forceinline__ void band_small_min(const FMM_LDS uint16_t *s_band, const FMM_LDS R *s_psi,
-                                               int n, int lane, R &m_out, uint32_t &k_out)
+                                               int n, int lane, R &m_out, uint32_t &k_out FMM_CYC_PARAM)
 {
     const int base = lane * S;
     uint32_t w[S > 1 ? S / 2 : 1];
@@ -327,6 +409,7 @@ __device__ __forceinline__ void band_small_min(const FMM_LDS uint16_t *s_band, c
     } else {
         w[0] = s_band[base];
     }
+    FMM_CYC(0);
     uint32_t ids[S];
     R vs[S];
 #pragma unroll
@@ -381,7 +464,7 @@ __device__ __forceinline__ void wave_pick(R bv, uint32_t bk, uint32_t &mh, uint3
 template <typename R, int W>
 __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band,
                                                   const uint16_t *g_band, int cap,
-                                                  const FMM_LDS R *s_psi, int n)
+                                                  const FMM_LDS R *s_psi, int n FMM_CYC_PARAM)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const R inf = (R)INFINITY;
@@ -389,23 +472,24 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
     uint32_t bk = ~0u;
     if (W == 1 && n <= 256 && n <= cap) {
         // a small band in LDS: 1, 2 or 4 slots per lane (n is wave-uniform)
-        if (n <= 64) band_small_min<R, 1>(s_band, s_psi, n, lane, bv, bk);
-        else if (n <= 128) band_small_min<R, 2>(s_band, s_psi, n, lane, bv, bk);
-        else band_small_min<R, 4>(s_band, s_psi, n, lane, bv, bk);
+        if (n <= 64) band_small_min<R, 1>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
+        else if (n <= 128) band_small_min<R, 2>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
+        else band_small_min<R, 4>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
     } else {
         // the first chunk of each wave sets (bv, bk) directly; later chunks (bands of
         // more than 512 * W slots) are merged in
         int c0 = wid * 512;
-        if (c0 < n) band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk);
+        if (c0 < n) band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk FMM_CYC_ARG);
         for (c0 += 512 * W; c0 < n; c0 += 512 * W) {
             R m;
             uint32_t km;
-            band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, m, km);
+            band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, m, km FMM_CYC_ARG);
             const bool better = (m < bv) | (val_eq(m, bv) & (km < bk));
             bv = better ? m : bv;
             bk = better ? km : bk;
         }
     }
+    FMM_CYC(1);
     uint32_t mh, ml, mk;
     wave_pick<R>(bv, bk, mh, ml, mk);
     uint32_t h = mh, l = ml;
@@ -434,6 +518,7 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
     h = __builtin_amdgcn_readfirstlane(h);
     l = __builtin_amdgcn_readfirstlane(l);
     mk = __builtin_amdgcn_readfirstlane(mk);
+    FMM_CYC(2);
     return MinPick<R>{KeyBits<R>::from(h, l), (int)(mk >> 16), (int)(mk & 0xffffu)};
 }
 

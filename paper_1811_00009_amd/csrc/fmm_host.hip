@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -483,20 +484,33 @@ int build_batch(int32_t nsolves, const fmm_problem *problems, int32_t block, dou
 // Autotuner cache: key -> (block, waves, ms), in memory and optionally in a text file.
 std::map<std::string, fmm_tuning> g_tune_cache;
 
+// The key holds the gcd of every side of every sample, so that a cached block size
+// divides the sides of any sample set that maps to the same key.
 std::string tune_key(const std::string &arch, int32_t dtype, int32_t nsamples, const fmm_problem *s)
 {
     double pts = 0;
-    int64_t smin = INT64_MAX, smax = 0;
+    int64_t smin = INT64_MAX, smax = 0, g = 0;
     for (int32_t q = 0; q < nsamples; ++q) {
         pts += (double)s[q].nx * s[q].ny * s[q].nz;
         smin = std::min<int64_t>(smin, std::min(s[q].nx, std::min(s[q].ny, s[q].nz)));
         smax = std::max<int64_t>(smax, std::max(s[q].nx, std::max(s[q].ny, s[q].nz)));
+        g = std::gcd(g, std::gcd(s[q].nx, std::gcd(s[q].ny, s[q].nz)));
     }
     char buf[256];
-    std::snprintf(buf, sizeof(buf), "%s:%s:n%d:pts2^%d:side%lld-%lld", arch.c_str(),
+    std::snprintf(buf, sizeof(buf), "%s:%s:n%d:pts2^%d:side%lld-%lld:gcd%lld", arch.c_str(),
                   dtype == FMM_F32 ? "f32" : "f64", (int)nsamples, (int)std::floor(std::log2(std::max(pts, 1.0))),
-                  (long long)smin, (long long)smax);
+                  (long long)smin, (long long)smax, (long long)g);
     return buf;
+}
+
+// A cached (block, waves) is used only if the block divides every side of the samples.
+bool tuning_fits(const fmm_tuning &t, int32_t nsamples, const fmm_problem *s)
+{
+    if (t.block <= 0) return false;
+    if (t.waves_per_block != 1 && t.waves_per_block != 2 && t.waves_per_block != 4) return false;
+    for (int32_t q = 0; q < nsamples; ++q)
+        if (s[q].nx % t.block || s[q].ny % t.block || s[q].nz % t.block) return false;
+    return true;
 }
 
 bool tune_file_lookup(const char *path, const std::string &key, fmm_tuning &t)
@@ -528,6 +542,21 @@ void tune_file_store(const char *path, const std::string &key, const fmm_tuning 
     std::fprintf(f, "%s %d %d %.6f\n", key.c_str(), t.block, t.waves_per_block, t.ms);
     std::fclose(f);
 }
+
+#ifdef FMM_CYCLES
+// s_memtime and the 100 MHz constant clock over the same ~20 ms spin.
+__global__ void k_clock_rate(unsigned long long *o)
+{
+    if (threadIdx.x != 0) return;
+    const unsigned long long m0 = __builtin_amdgcn_s_memtime(), w0 = wall_clock64();
+    while (wall_clock64() - w0 < 2000000ull) __builtin_amdgcn_s_sleep(10);
+    const unsigned long long m1 = __builtin_amdgcn_s_memtime(), w1 = wall_clock64();
+    o[0] = m0;
+    o[1] = m1;
+    o[2] = w0;
+    o[3] = w1;
+}
+#endif
 
 } // namespace
 
@@ -658,16 +687,17 @@ int fmm_autotune(int32_t nsamples, const fmm_problem *samples, int32_t dtype, co
         if (int rc = device_info(dev)) return rc;
         const std::string key = tune_key(dev.name, dtype, nsamples, samples);
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
+        if (it != g_tune_cache.end() && tuning_fits(it->second, nsamples, samples)) {
             *out = it->second;
             return 0;
         }
         fmm_tuning best{0, 0, INFINITY};
-        if (tune_file_lookup(cache_path, key, best)) {
+        if (tune_file_lookup(cache_path, key, best) && tuning_fits(best, nsamples, samples)) {
             g_tune_cache[key] = best;
             *out = best;
             return 0;
         }
+        best = fmm_tuning{0, 0, INFINITY};
         const int blocks[2] = {8, 16};
         const int waves[3] = {1, 2, 4};
         for (int B : blocks) {
@@ -749,5 +779,35 @@ const char *fmm_strerror(int code)
 const char *fmm_last_error_detail(void) { return g_detail.c_str(); }
 
 const char *fmm_version(void) { return "fmm-mi355x 0.1 (gfx950)"; }
+
+#ifdef FMM_CYCLES
+// Profiling build only.  out[k] = segment k summed over every work-group since the last
+// reset (see the account's segments in fmm_device.hpp); out[16] = shader-clock ticks
+// per second of s_memtime, measured against the 100 MHz constant clock.
+int fmm_cycle_account(unsigned long long *out, int reset)
+{
+    static unsigned long long rows[kCycRows][kCycSegs];
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpyFromSymbol(rows, HIP_SYMBOL(fmm_cyc_rows), sizeof(rows)));
+    for (int k = 0; k < kCycSegs; ++k) {
+        unsigned long long acc = 0;
+        for (int w = 0; w < kCycRows; ++w) acc += rows[w][k];
+        out[k] = acc;
+    }
+    unsigned long long *clk = nullptr;
+    HIPCHK(hipMalloc(&clk, 4 * sizeof(unsigned long long)));
+    k_clock_rate<<<1, 64>>>(clk);
+    HIPCHK(hipGetLastError());
+    unsigned long long h[4];
+    HIPCHK(hipMemcpy(h, clk, sizeof(h), hipMemcpyDeviceToHost));
+    (void)hipFree(clk);
+    out[16] = (unsigned long long)((double)(h[1] - h[0]) / (double)(h[3] - h[2]) * 1e8);
+    if (reset) {
+        std::memset(rows, 0, sizeof(rows));
+        HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(fmm_cyc_rows), rows, sizeof(rows)));
+    }
+    return 0;
+}
+#endif
 
 } // extern "C"

@@ -128,7 +128,7 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
 template <typename R, int B, int W>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
                             int c, char *smem, unsigned long long &pops_acc, bool &a_out,
-                            int &n_out, int &pops_out)
+                            int &n_out, int &pops_out FMM_CYC_PARAM)
 {
     using L = Lds<R, B, W>;
     using Gm = Geo<B>;
@@ -148,6 +148,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     uint16_t *g_band = kp.band_t + ib * (int64_t)BAND;
     const R *g_rhs = kp.rhs_t + ib * (int64_t)T;
 
+    FMM_CYC_START();
     int n = kp.band_n[ib];
     copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_psi),
                                                reinterpret_cast<const v4u *>(g_psi), tid);
@@ -172,6 +173,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         asm volatile("" ::"v"(acc));  // keeps the loads (the ghost slots of the tile are unset)
     }
     __syncthreads();
+    FMM_CYC_FULL(6);
+    FMM_CYC_COUNT(13, 1);
 
     // per-lane neighbour direction of Update_Neighbors: lanes 0-5 = -x, +x, -y, +y, -z, +z
     const int dI = (lane == 1) - (lane == 0), dJ = (lane == 3) - (lane == 2),
@@ -190,7 +193,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             exit_min = inf;
             break;
         }
-        const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n);
+        const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n FMM_CYC_ARG);
         if (mp.v > rbound) {  // beyond the restart bound: stop (deactivate past width)
             if ((double)mp.v > pd.width) active = false;
             exit_min = mp.v;
@@ -263,8 +266,11 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             }
             if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
                 s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
+            FMM_CYC(3);
+            FMM_CYC_COUNT(12, 1);
             bool ins = false;
             if (inb && (tq & kStatus) != kKnownFix && psq > mp.v) {
+                FMM_CYC_LSTART();
                 R c[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
@@ -286,13 +292,18 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     }
                     c[ax] = axis_candidate<R>(psq, lo[ax], klo, hi[ax], khi);
                 }
+                FMM_CYC_L(8);
+                FMM_CYC_LFULL(9);
                 const R t = quad_root<R>(c[0], c[1], c[2], rhs);
                 if (t < psq) {
                     s_psi[q] = t;
                     s_tag[q] = kBand | kInBand;
                     ins = !(tq & kInBand);
                 }
+                FMM_CYC_L(10);
+                FMM_CYC_COUNT(11, 1);
             }
+            FMM_CYC(4);
             const uint64_t bal = ballot(ins);
             if (ins) {
                 const int at = n + (int)lanes_below(bal);
@@ -319,6 +330,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
+        FMM_CYC(5);
     }
 
     // Upsilon on the faces: a face is touched exactly when one of its boundary points got a
@@ -384,6 +396,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     pops_acc += (unsigned long long)npops;
     if (kp.nprob > 1 && tid == 0) atomicAdd(&kp.prob_pops[kp.blk_prob[ib]], (unsigned long long)npops);
     __syncthreads();  // LDS is reused by the next block
+    FMM_CYC_FULL(7);
 }
 
 // ---------------------------------------------------------------- Alg. 5 on one block
@@ -548,7 +561,7 @@ __device__ __forceinline__ void flush_features(Ctl *ctl, int cn, const unsigned 
 // only activate a block, never deactivate it).
 template <typename R, int B, int W>
 __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char *smem, int G, int w,
-                            Totals &tot)
+                            Totals &tot FMM_CYC_PARAM)
 {
     const int c = (int)(r & 1);
     const int tid = threadIdx.x;
@@ -621,7 +634,7 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         }
         bool a;
         int nb, np;
-        march_block<R, B, W>(kp, ib, pd, bound, c, smem, pops, a, nb, np);
+        march_block<R, B, W>(kp, ib, pd, bound, c, smem, pops, a, nb, np FMM_CYC_ARG);
         if (tid == 0 && a) append_next<R>(kp, c, r, ib, max(np, nb), nb, s_feat);
     }
     if (tid == 0 && kp.want_features) flush_features(ctl, c ^ 1, s_feat);
@@ -741,6 +754,7 @@ __global__ void __launch_bounds__(64 * W)
     const ProbDesc &p0 = kp.prob[0];
     double prev_bound = 0.0, lstride = p0.stride, lbound = 0.0;
     Totals tot;
+    FMM_CYC_DECL;
     for (int64_t r = 1;; ++r) {
         const int c = (int)(r & 1);
         if (kp.stride_mode) {
@@ -761,7 +775,7 @@ __global__ void __launch_bounds__(64 * W)
         }
         const int ncur = __hip_atomic_load(&ctl->n_list[c], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
-        march_phase<R, B, W>(kp, r, lbound, smem, G, w, tot);
+        march_phase<R, B, W>(kp, r, lbound, smem, G, w, tot FMM_CYC_ARG);
         grid_barrier(ctl, (unsigned)G, kp.timeout_ticks);
         if (read_abort(ctl)) break;
         // list[c] has been consumed: clear its counters for restart r + 1, which appends
@@ -823,6 +837,9 @@ __global__ void __launch_bounds__(64 * W)
         }
     }
     if (tid == 0) flush_totals(ctl, tot);
+#ifdef FMM_CYCLES
+    cyc.flush();
+#endif
 }
 
 // ---------------------------------------------------------------- host-driven loop
@@ -848,7 +865,8 @@ __global__ void __launch_bounds__(64 * W)
     extern __shared__ __align__(16) char smem[];
     if (read_abort(kp.ctl)) return;
     Totals tot;
-    march_phase<R, B, W>(kp, r, 0.0, smem, (int)gridDim.x, (int)blockIdx.x, tot);
+    FMM_CYC_DECL;
+    march_phase<R, B, W>(kp, r, 0.0, smem, (int)gridDim.x, (int)blockIdx.x, tot FMM_CYC_ARG);
     if (threadIdx.x == 0) flush_totals(kp.ctl, tot);
 }
 
@@ -986,7 +1004,8 @@ __global__ void __launch_bounds__(64) k_argmin_probe(const R *psi, const uint16_
     for (int t = threadIdx.x; t < Gm::T; t += 64) s_psi[t] = t == 0 ? (R)INFINITY : psi[t];
     for (int k = threadIdx.x; k < Gm::BANDC; k += 64) s_band[k] = k < n ? band[k] : (uint16_t)0;
     __syncthreads();
-    const MinPick<R> mp = band_argmin<R, 1>(s_band, band, cap, s_psi, n);
+    FMM_CYC_DECL;
+    const MinPick<R> mp = band_argmin<R, 1>(s_band, band, cap, s_psi, n FMM_CYC_ARG);
     if (threadIdx.x == 0) {
         vout[0] = mp.v;
         iout[0] = mp.idx;

@@ -1,0 +1,73 @@
+"""The paper's four test cases (Sec. 3.1) at 512^3 in FP64, the precision the paper
+computes in, on grids of the size it measures.
+
+* For 8^3 and 16^3 blocks with the stride 2h: psi bitwise equal to the block method
+  of Alg. 6 run on the host (the OpenMP block solver, bitwise the sequential block
+  reference), with the same restart and pop counts.
+* Cases 2 and 4 (the fast-varying speed and the F = 0 barriers) also against the
+  single-heap baseline solver on every point: max |diff| <= 1e-12, unreached points
+  +inf on both sides (Sec. 3.2: multi-block results agree with the baseline to
+  rounding).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1811_00009_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N = 512
+
+
+def _log(msg):
+    print(f"[paper-scale] {msg}", flush=True)
+
+
+def _gpu_solve(fmm, p, block):
+    import torch
+    F = torch.from_numpy(p.F).cuda()
+    psi, st = fmm.solve(F, p.h, p.sources, block=block, stride=2 * p.h, with_stats=True)
+    torch.cuda.synchronize()
+    out = psi.cpu().numpy()
+    del F, psi
+    return out, st
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("block", [8, 16])
+@pytest.mark.parametrize("case", [1, 2, 3, 4])
+def test_paper_case_512_fp64_bitwise_block_reference(fmm_lib, case, block):
+    p = inputs.paper_case(case, N)
+    _log(f"case {case}, {N}^3 FP64, block {block}, 2h: GPU solve")
+    got, st = _gpu_solve(fmm_lib, p, block)
+    t0 = time.perf_counter()
+    ref, rs = oracle.block_fmm_parallel(p.F, p.h, p.sources, block=block, stride=2 * p.h,
+                                        stats=True)
+    _log(f"case {case}: host block solver {time.perf_counter() - t0:.1f} s on {rs['threads']} "
+         f"threads; restarts {st['restarts']} / {rs['restarts']}, pops {st['pops']} / {rs['pops']}")
+    assert st["restarts"] == rs["restarts"]
+    assert st["pops"] == rs["pops"]
+    if not np.array_equal(got.view(np.uint64), ref.view(np.uint64)):
+        k, j, i = np.argwhere(got.view(np.uint64) != ref.view(np.uint64))[0]
+        raise AssertionError(f"psi differs at ({i}, {j}, {k}): {got[k, j, i]!r} vs {ref[k, j, i]!r}")
+    if case == 4:
+        assert np.isinf(got).any()  # points inside the barriers stay unreached
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("case", [2, 4])
+def test_paper_case_512_fp64_single_heap_baseline(fmm_lib, case):
+    p = inputs.paper_case(case, N)
+    _log(f"case {case}, {N}^3 FP64, block 8, 2h: GPU solve")
+    got, st = _gpu_solve(fmm_lib, p, 8)
+    t0 = time.perf_counter()
+    base = oracle.fmm(p.F, p.h, p.sources)
+    _log(f"case {case}: single-heap baseline {time.perf_counter() - t0:.1f} s")
+    assert np.array_equal(np.isinf(got), np.isinf(base))
+    fin = np.isfinite(base)
+    err = float(np.max(np.abs(got[fin] - base[fin])))
+    _log(f"case {case}: max |GPU - baseline| = {err:.3e}")
+    assert err <= 1e-12, err
