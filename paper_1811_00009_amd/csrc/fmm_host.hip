@@ -70,12 +70,82 @@ int ensure(DevBuf &b, size_t bytes, const char *what)
     return 0;
 }
 
-// Library-owned device memory of one GPU, grown on demand and kept for reuse.
+// Library-owned device memory of one GPU: one arena, grown on demand and kept for
+// reuse, that every launch carves its buffers from (ws_layout).
 struct Workspace {
-    DevBuf psi, tag, band, bandn, rhs, bmin, A, Cm, bprob, fmean, lastpops, list0, list1, xlist, ctl, prob,
-        src, plastr, ppops;
+    DevBuf arena;
     hipEvent_t e0 = nullptr, e1 = nullptr, l0 = nullptr, l1 = nullptr;
 };
+
+// Buffers of one launch, each at a 256-byte aligned offset from one base address.
+enum WsBuf {
+    kWsPsi, kWsTag, kWsBand, kWsBandN, kWsRhs, kWsBmin, kWsA, kWsCm, kWsBprob, kWsFmean,
+    kWsLastpops, kWsList0, kWsList1, kWsXlist, kWsCtl, kWsProb, kWsSrc, kWsPlastr, kWsPpops,
+    kWsCount
+};
+
+struct WsLayout {
+    size_t off[kWsCount];
+    size_t total;
+};
+
+template <typename R, int B>
+WsLayout ws_layout(int64_t nblk, int32_t nprob, size_t nents)
+{
+    constexpr size_t T = Geo<B>::T, BAND = Geo<B>::BAND, TAGB = Geo<B>::TAGB;
+    const size_t nb = (size_t)nblk, np = (size_t)nprob;
+    size_t bytes[kWsCount];
+    bytes[kWsPsi] = nb * T * sizeof(R);
+    bytes[kWsTag] = nb * TAGB;
+    bytes[kWsBand] = nb * BAND * 2;
+    bytes[kWsBandN] = nb * 4;
+    bytes[kWsRhs] = nb * T * sizeof(R);
+    bytes[kWsBmin] = nb * sizeof(R);
+    bytes[kWsA] = nb;
+    bytes[kWsCm] = nb * 4;
+    bytes[kWsBprob] = nb * 4;
+    bytes[kWsFmean] = nb * 4;
+    bytes[kWsLastpops] = nb * 4;
+    bytes[kWsList0] = nb * 4 * 4;  // 4 work bins
+    bytes[kWsList1] = nb * 4 * 4;
+    bytes[kWsXlist] = nb * 4;
+    bytes[kWsCtl] = sizeof(Ctl);
+    bytes[kWsProb] = sizeof(ProbDesc) * np;
+    bytes[kWsSrc] = sizeof(SrcEntry) * std::max<size_t>(1, nents);
+    bytes[kWsPlastr] = sizeof(int32_t) * np;
+    bytes[kWsPpops] = sizeof(unsigned long long) * np;
+    WsLayout L;
+    size_t at = 0;
+    for (int k = 0; k < kWsCount; ++k) {
+        L.off[k] = at;
+        at += (bytes[k] + 255) / 256 * 256;
+    }
+    L.total = at;
+    return L;
+}
+
+template <typename R>
+void ws_bind(KParams<R> &kp, char *base, const WsLayout &L)
+{
+    kp.psi_t = (R *)(base + L.off[kWsPsi]);
+    kp.tag_t = (uint8_t *)(base + L.off[kWsTag]);
+    kp.band_t = (uint16_t *)(base + L.off[kWsBand]);
+    kp.band_n = (int32_t *)(base + L.off[kWsBandN]);
+    kp.rhs_t = (R *)(base + L.off[kWsRhs]);
+    kp.bmin = (R *)(base + L.off[kWsBmin]);
+    kp.A = (uint8_t *)(base + L.off[kWsA]);
+    kp.Cm = (uint32_t *)(base + L.off[kWsCm]);
+    kp.blk_prob = (int32_t *)(base + L.off[kWsBprob]);
+    kp.fmean = (float *)(base + L.off[kWsFmean]);
+    kp.lastpops = (int32_t *)(base + L.off[kWsLastpops]);
+    kp.list0 = (int32_t *)(base + L.off[kWsList0]);
+    kp.list1 = (int32_t *)(base + L.off[kWsList1]);
+    kp.xlist = (int32_t *)(base + L.off[kWsXlist]);
+    kp.ctl = (Ctl *)(base + L.off[kWsCtl]);
+    kp.prob = (const ProbDesc *)(base + L.off[kWsProb]);
+    kp.prob_lastr = (int32_t *)(base + L.off[kWsPlastr]);
+    kp.prob_pops = (unsigned long long *)(base + L.off[kWsPpops]);
+}
 
 std::mutex g_mu;
 std::map<int, Workspace> g_ws;
@@ -213,123 +283,100 @@ struct RunOut {
     std::vector<unsigned long long> ppops;
 };
 
-template <typename R, int B, int W>
-int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, RunOut &out)
+// Block ranges of the problems in the pooled arrays; returns the block count.
+int64_t assign_blocks(ProbDesc *d, int32_t nprob, int B)
 {
-    constexpr int T = Geo<B>::T, B3 = Geo<B>::B3, BAND = Geo<B>::BAND, TAGB = Geo<B>::TAGB;
-    using L = Lds<R, B, W>;
-    Device dev;
-    if (int rc = device_info(dev)) return rc;
-    std::lock_guard<std::mutex> lock(g_mu);
-    Workspace &ws = g_ws[dev.id];
-
-    // block ranges of the problems in the pooled arrays
     int64_t nblk = 0;
-    for (Prob &pb : probs) {
-        ProbDesc &d = pb.d;
-        d.mx = d.nx / B;
-        d.my = d.ny / B;
-        d.mz = d.nz / B;
-        d.blk0 = nblk;
-        d.nblk = (int64_t)d.mx * d.my * d.mz;
-        d.nmax = std::max(d.nx, std::max(d.ny, d.nz));
-        nblk += d.nblk;
+    for (int32_t q = 0; q < nprob; ++q) {
+        d[q].mx = d[q].nx / B;
+        d[q].my = d[q].ny / B;
+        d[q].mz = d[q].nz / B;
+        d[q].blk0 = nblk;
+        d[q].nblk = (int64_t)d[q].mx * d[q].my * d[q].mz;
+        d[q].nmax = std::max(d[q].nx, std::max(d[q].ny, d[q].nz));
+        nblk += d[q].nblk;
     }
-    if (nblk >= ((int64_t)1 << 31)) return fail(FMM_EINVAL, "too many blocks");
-    const int32_t nprob = (int32_t)probs.size();
+    return nblk;
+}
 
-    int rc = 0;
-    if ((rc = ensure(ws.psi, (size_t)nblk * T * sizeof(R), "psi tiles")) ||
-        (rc = ensure(ws.tag, (size_t)nblk * TAGB, "tag tiles")) ||
-        (rc = ensure(ws.band, (size_t)nblk * BAND * 2, "band arrays")) ||
-        (rc = ensure(ws.bandn, (size_t)nblk * 4, "band sizes")) ||
-        (rc = ensure(ws.rhs, (size_t)nblk * T * sizeof(R), "rhs tiles")) ||
-        (rc = ensure(ws.bmin, (size_t)nblk * sizeof(R), "band minima")) ||
-        (rc = ensure(ws.A, (size_t)nblk, "activation flags")) ||
-        (rc = ensure(ws.Cm, (size_t)nblk * 4, "exchange flags")) ||
-        (rc = ensure(ws.bprob, (size_t)nblk * 4, "block problems")) ||
-        (rc = ensure(ws.fmean, (size_t)nblk * 4, "block speeds")) ||
-        (rc = ensure(ws.lastpops, (size_t)nblk * 4, "block work estimates")) ||
-        (rc = ensure(ws.list0, (size_t)nblk * 4 * 4, "march list 0")) ||
-        (rc = ensure(ws.list1, (size_t)nblk * 4 * 4, "march list 1")) ||
-        (rc = ensure(ws.xlist, (size_t)nblk * 4, "exchange list")) ||
-        (rc = ensure(ws.ctl, sizeof(Ctl), "control block")) ||
-        (rc = ensure(ws.prob, sizeof(ProbDesc) * nprob, "problem table")) ||
-        (rc = ensure(ws.plastr, sizeof(int32_t) * nprob, "problem restarts")) ||
-        (rc = ensure(ws.ppops, sizeof(unsigned long long) * nprob, "problem pops")))
-        return rc;
-    if (!ws.e0) {
-        HIPCHK(hipEventCreate(&ws.e0));
-        HIPCHK(hipEventCreate(&ws.e1));
-        HIPCHK(hipEventCreate(&ws.l0));
-        HIPCHK(hipEventCreate(&ws.l1));
-    }
+// Fills n 32-bit words with zero (used instead of a memset node, which callers that
+// capture the stream into a graph cannot rely on).
+__global__ void k_clear_words(uint32_t *p, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
 
-    std::vector<SrcEntry> ents;
-    std::vector<int32_t> first;
-    build_sources(probs, B, ents, first);
-    if ((rc = ensure(ws.src, sizeof(SrcEntry) * std::max<size_t>(1, ents.size()), "sources")))
-        return rc;
+// Host data of one launch.
+struct LaunchIn {
+    const ProbDesc *descs;
+    int32_t nprob;
+    int64_t nblk;
+    const SrcEntry *ents;
+    int32_t nents;
+    SrcEntry *ents_dev;    // device copy of ents (a carved buffer)
+    const int32_t *first;  // blocks of the first march list
+    int32_t nfirst;
+    const fmm_options *o;
+};
 
-    std::vector<ProbDesc> descs(nprob);
-    for (int32_t q = 0; q < nprob; ++q) descs[q] = probs[q].d;
+// Events around the launch (all null: no timing).
+struct LaunchEvents {
+    hipEvent_t e0 = nullptr, e1 = nullptr, l0 = nullptr, l1 = nullptr;
+};
+
+// The launch itself, on buffers already carved (kp bound by ws_bind): copy the problem
+// table, the source entries, the first march list and the control block to the device,
+// set up every block (Alg. 1), run the restart loop (Alg. 6) and copy psi back to the
+// callers' linear layout.  Allocates no device memory.  Returns with the stream drained
+// and ctl_out filled; the device error code, if any, is in ctl_out.abort.
+template <typename R, int B, int W>
+int launch_solve(KParams<R> &kp, const LaunchIn &in, const Device &dev, hipStream_t st,
+                 const LaunchEvents &ev, Ctl &ctl_out, int &grid_out)
+{
+    using L = Lds<R, B, W>;
+    const fmm_options &o = *in.o;
+    const int64_t nblk = in.nblk;
     Ctl hc;
     std::memset(&hc, 0, sizeof(hc));
-    hc.n_list[1] = (int)first.size();  // restart 1 marches list[1] (all in bin 0)
-    hc.bin_n[1][0] = (int)first.size();
+    hc.n_list[1] = in.nfirst;  // restart 1 marches list[1] (all in bin 0)
+    hc.bin_n[1][0] = in.nfirst;
     hc.rmin[0] = hc.rmin[1] = ~0ull;
 
-    HIPCHK(hipMemcpyAsync(ws.prob.p, descs.data(), sizeof(ProbDesc) * nprob, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ws.src.p, ents.data(), sizeof(SrcEntry) * ents.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ws.list1.p, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ws.ctl.p, &hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(ws.plastr.p, 0, sizeof(int32_t) * nprob, st));
-    HIPCHK(hipMemsetAsync(ws.ppops.p, 0, sizeof(unsigned long long) * nprob, st));
+    HIPCHK(hipMemcpyAsync((void *)kp.prob, in.descs, sizeof(ProbDesc) * in.nprob, hipMemcpyHostToDevice, st));
+    if (in.nents > 0)
+        HIPCHK(hipMemcpyAsync(in.ents_dev, in.ents, sizeof(SrcEntry) * in.nents, hipMemcpyHostToDevice, st));
+    if (in.nfirst > 0)
+        HIPCHK(hipMemcpyAsync(kp.list1, in.first, sizeof(int32_t) * in.nfirst, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(kp.ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    k_clear_words<<<1, 256, 0, st>>>((uint32_t *)kp.prob_lastr, in.nprob);
+    k_clear_words<<<1, 256, 0, st>>>((uint32_t *)kp.prob_pops, 2 * (int64_t)in.nprob);
 
-    KParams<R> kp{};
-    kp.psi_t = (R *)ws.psi.p;
-    kp.tag_t = (uint8_t *)ws.tag.p;
-    kp.band_t = (uint16_t *)ws.band.p;
-    kp.band_n = (int32_t *)ws.bandn.p;
-    kp.rhs_t = (R *)ws.rhs.p;
-    kp.bmin = (R *)ws.bmin.p;
-    kp.A = (uint8_t *)ws.A.p;
-    kp.Cm = (uint32_t *)ws.Cm.p;
-    kp.blk_prob = (int32_t *)ws.bprob.p;
-    kp.fmean = (float *)ws.fmean.p;
-    kp.lastpops = (int32_t *)ws.lastpops.p;
-    kp.list0 = (int32_t *)ws.list0.p;
-    kp.list1 = (int32_t *)ws.list1.p;
-    kp.xlist = (int32_t *)ws.xlist.p;
-    kp.ctl = (Ctl *)ws.ctl.p;
-    kp.prob = (const ProbDesc *)ws.prob.p;
-    kp.nprob = nprob;
+    kp.nprob = in.nprob;
     kp.stride_mode = o.stride_mode == FMM_STRIDE_LEARNED ? 1 : 0;
     kp.nblk = nblk;
     kp.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000000;
-    kp.pop_cap = (int64_t)64 * T;
+    kp.pop_cap = (int64_t)64 * Geo<B>::T;
     kp.timeout_ticks = dev.ticks_per_s * 10;
     kp.mlp = (const float *)o.mlp_weights;
     kp.trace = o.trace_dev;
     kp.trace_cap = o.trace_dev ? o.trace_cap : 0;
     kp.want_features = (kp.trace_cap > 0 || kp.stride_mode) ? 1 : 0;
     kp.band_cap = o.band_lds_cap;
-    kp.prob_lastr = (int32_t *)ws.plastr.p;
-    kp.prob_pops = (unsigned long long *)ws.ppops.p;
 
     const size_t lds = L::bytes;
-    HIPCHK(hipEventRecord(ws.e0, st));
+    if (ev.e0) HIPCHK(hipEventRecord(ev.e0, st));
     k_fill_blkprob<R><<<(unsigned)std::min<int64_t>((nblk + 255) / 256, 4096), 256, 0, st>>>(
-        kp.blk_prob, kp.prob, nprob, nblk);
+        kp.blk_prob, kp.prob, in.nprob, nblk);
     k_init<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
-    if (!ents.empty())
-        k_sources<R, B><<<(unsigned)((ents.size() + 127) / 128), 128, 0, st>>>(
-            kp, (const SrcEntry *)ws.src.p, (int32_t)ents.size());
+    if (in.nents > 0)
+        k_sources<R, B><<<(unsigned)((in.nents + 127) / 128), 128, 0, st>>>(kp, in.ents_dev, in.nents);
     HIPCHK(hipGetLastError());
 
     int per_cu = 0;
     int grid = 0;
-    HIPCHK(hipEventRecord(ws.l0, st));
+    if (ev.l0) HIPCHK(hipEventRecord(ev.l0, st));
     if (o.launch_mode == FMM_LAUNCH_PERSISTENT) {
         auto kern = k_persistent<R, B, W>;
         HIPCHK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -350,8 +397,8 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
         HIPCHK(hipFuncSetAttribute((const void *)kx, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, km, 64 * W, lds));
         const int64_t cap = std::max<int64_t>(1, (int64_t)std::max(per_cu, 1) * dev.cus);
-        int ncur = (int)first.size();
-        Ctl *dctl = (Ctl *)ws.ctl.p;
+        int ncur = in.nfirst;
+        Ctl *dctl = kp.ctl;
         int64_t r = 1;
         for (;; ++r) {
             const int c = (int)(r & 1);
@@ -374,24 +421,62 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
                 break;
             }
         }
-        const double fb = std::min((double)r * probs[0].d.stride, probs[0].d.width);
+        const double fb = std::min((double)r * in.descs[0].stride, in.descs[0].width);
         long long rr = r;
         HIPCHK(hipMemcpyAsync(&dctl->restarts, &rr, sizeof(rr), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(&dctl->final_bound, &fb, sizeof(fb), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // rr and fb live on this stack frame
     }
-    HIPCHK(hipEventRecord(ws.l1, st));
+    if (ev.l1) HIPCHK(hipEventRecord(ev.l1, st));
     k_unlayout<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipEventRecord(ws.e1, st));
-    HIPCHK(hipMemcpyAsync(&out.ctl, ws.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    if (ev.e1) HIPCHK(hipEventRecord(ev.e1, st));
+    HIPCHK(hipMemcpyAsync(&ctl_out, kp.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    grid_out = grid;
+    return 0;
+}
+
+// A solve on the library's cached arena (allocated and grown on demand).
+template <typename R, int B, int W>
+int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, RunOut &out)
+{
+    Device dev;
+    if (int rc = device_info(dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace &ws = g_ws[dev.id];
+
+    const int32_t nprob = (int32_t)probs.size();
+    std::vector<ProbDesc> descs(nprob);
+    for (int32_t q = 0; q < nprob; ++q) descs[q] = probs[q].d;
+    const int64_t nblk = assign_blocks(descs.data(), nprob, B);
+    if (nblk >= ((int64_t)1 << 31)) return fail(FMM_EINVAL, "too many blocks");
+    for (int32_t q = 0; q < nprob; ++q) probs[q].d = descs[q];
+
+    std::vector<SrcEntry> ents;
+    std::vector<int32_t> first;
+    build_sources(probs, B, ents, first);
+    const WsLayout Lw = ws_layout<R, B>(nblk, nprob, ents.size());
+    if (int rc = ensure(ws.arena, Lw.total, "workspace")) return rc;
+    if (!ws.e0) {
+        HIPCHK(hipEventCreate(&ws.e0));
+        HIPCHK(hipEventCreate(&ws.e1));
+        HIPCHK(hipEventCreate(&ws.l0));
+        HIPCHK(hipEventCreate(&ws.l1));
+    }
+    KParams<R> kp{};
+    char *base = (char *)ws.arena.p;
+    ws_bind<R>(kp, base, Lw);
+    LaunchIn in{descs.data(), nprob, nblk, ents.data(), (int32_t)ents.size(),
+                (SrcEntry *)(base + Lw.off[kWsSrc]), first.data(), (int32_t)first.size(), &o};
+    LaunchEvents ev{ws.e0, ws.e1, ws.l0, ws.l1};
+    if (int rc = launch_solve<R, B, W>(kp, in, dev, st, ev, out.ctl, out.grid)) return rc;
     out.lastr.resize(nprob);
     out.ppops.resize(nprob);
-    HIPCHK(hipMemcpyAsync(out.lastr.data(), ws.plastr.p, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(out.ppops.data(), ws.ppops.p, sizeof(unsigned long long) * nprob, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemcpy(out.lastr.data(), kp.prob_lastr, sizeof(int32_t) * nprob, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(out.ppops.data(), kp.prob_pops, sizeof(unsigned long long) * nprob, hipMemcpyDeviceToHost));
     HIPCHK(hipEventElapsedTime(&out.ms, ws.e0, ws.e1));
     HIPCHK(hipEventElapsedTime(&out.loop_ms, ws.l0, ws.l1));
-    out.grid = grid;
     return map_device_error(out.ctl.abort);
 }
 

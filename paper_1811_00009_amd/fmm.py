@@ -80,6 +80,11 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # torch first: the library's HIP runtime dependency (soname libamdhip64.so.7) then
+    # binds to the runtime torch already mapped, so that both share one runtime, one
+    # device context and the streams passed in.  Loaded the other way round, the
+    # process maps two HIP runtimes and the second one to open the device finds none.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                            "(run __graft_entry__.build() or paper_1811_00009_amd/build.py)")
