@@ -36,6 +36,7 @@
 #ifndef FMM_H
 #define FMM_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -146,6 +147,28 @@ void fmm_options_default(fmm_options *opt);
 int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
               const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
               void *hip_stream, const fmm_options *opt, fmm_stats *stats);
+
+/*
+ * fmm_solve without any device allocation, for callers that cannot allocate: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, semantics and errors as fmm_solve, with these differences:
+ *  * the library's device workspace comes from one static device array of
+ *    FMM_NOALLOC_SCRATCH_BYTES per GPU, which each GPU that loads the library holds
+ *    until the process ends; no hipMalloc, hipFree, event or other allocating
+ *    runtime call is made;
+ *  * a grid whose workspace does not fit (about 4.2e6 points at block 16 and 3.1e6
+ *    at block 8 in FP32, half that in FP64) fails with FMM_ENOMEM before any device
+ *    work, and at most 256 sources are accepted (FMM_EINVAL beyond);
+ *  * stats->elapsed_ms and stats->loop_ms are 0 (the call is not timed);
+ *  * every call on a GPU uses that GPU's one array and leaves the last call's data in
+ *    it; calls are serialised by the library's lock, but calls whose work overlaps on
+ *    one GPU (another process excepted, which has its own array) would race.
+ * The result is bitwise that of fmm_solve with the same arguments (same kernels).
+ */
+#define FMM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int fmm_solve_noalloc(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
+                      const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
+                      void *hip_stream, const fmm_options *opt, fmm_stats *stats);
 
 /* One problem of a batch (same meaning as the fmm_solve arguments).
    The stride of each problem is its own; dtype must be the same across a batch. */

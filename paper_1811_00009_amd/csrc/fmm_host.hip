@@ -480,6 +480,128 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     return map_device_error(out.ctl.abort);
 }
 
+// ---------------------------------------------------------------- no-allocation solve
+// Device memory of fmm_solve_noalloc: one fixed array per GPU, held from the library's
+// first kernel launch on that GPU until the process ends.  Host code never uses the
+// name `scratch` as an address (it is a host-side stand-in): the device address comes
+// from hipGetSymbolAddress, once per device, and is kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[FMM_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch` per device; under g_mu
+
+// Device address of this device's scratch array (dev is the current device).
+int scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(FMM_ENOTSUP, "fmm_solve_noalloc: device index too large");
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FMM_EHIP, std::string("fmm_solve_noalloc: hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+constexpr int kNoallocMaxSources = 256;
+constexpr int kNoallocMaxEntries = 4 * kNoallocMaxSources;  // own block + up to 3 ghost faces
+
+// build_sources for one problem into fixed arrays: the same entries, sorted by
+// (block, tile point), repeated points keeping the smallest value.
+int build_sources_fixed(const ProbDesc &d, const fmm_source *src, int32_t nsrc, int B,
+                        SrcEntry *out, int32_t &nout, int32_t *first, int32_t &nfirst)
+{
+    const int P = B + 2;
+    nout = 0;
+    for (int32_t q = 0; q < nsrc; ++q) {
+        const fmm_source &s = src[q];
+        for (int64_t bz = s.k / B - 1; bz <= s.k / B + 1; ++bz)
+            for (int64_t by = s.j / B - 1; by <= s.j / B + 1; ++by)
+                for (int64_t bx = s.i / B - 1; bx <= s.i / B + 1; ++bx) {
+                    if (bx < 0 || by < 0 || bz < 0 || bx >= d.mx || by >= d.my || bz >= d.mz) continue;
+                    const int64_t li = s.i - bx * B + 1, lj = s.j - by * B + 1, lk = s.k - bz * B + 1;
+                    if (li < 0 || lj < 0 || lk < 0 || li > B + 1 || lj > B + 1 || lk > B + 1) continue;
+                    const int ng = (li == 0 || li == B + 1) + (lj == 0 || lj == B + 1) +
+                                   (lk == 0 || lk == B + 1);
+                    if (ng > 1) continue;
+                    if (nout >= kNoallocMaxEntries)
+                        return fail(FMM_EINVAL, "fmm_solve_noalloc: too many source entries");
+                    SrcEntry &e = out[nout++];
+                    e.ib = d.blk0 + bx + (int64_t)d.mx * (by + (int64_t)d.my * bz);
+                    e.t = (int32_t)(li + P * (lj + P * lk));
+                    e.pad = 0;
+                    e.v = s.psi0 + 0.0;  // -0 -> +0
+                }
+    }
+    std::sort(out, out + nout, [](const SrcEntry &a, const SrcEntry &b) {
+        return a.ib != b.ib ? a.ib < b.ib : (a.t != b.t ? a.t < b.t : a.v < b.v);
+    });
+    int32_t m = 0;
+    for (int32_t k = 0; k < nout; ++k)  // the first of equal (block, point) keeps the least value
+        if (m == 0 || out[m - 1].ib != out[k].ib || out[m - 1].t != out[k].t) out[m++] = out[k];
+    nout = m;
+    nfirst = 0;
+    for (int32_t k = 0; k < nout; ++k)
+        if (nfirst == 0 || first[nfirst - 1] != (int32_t)out[k].ib) first[nfirst++] = (int32_t)out[k].ib;
+    return 0;
+}
+
+template <typename R, int B, int W>
+int run_solve_noalloc(const ProbDesc &d0, const fmm_source *src, int32_t nsrc, const fmm_options &o,
+                      hipStream_t st, Ctl &ctl_out, int &grid_out)
+{
+    ProbDesc d = d0;
+    const int64_t nblk = assign_blocks(&d, 1, B);
+    SrcEntry ents[kNoallocMaxEntries];
+    int32_t first[kNoallocMaxEntries];
+    int32_t nents = 0, nfirst = 0;
+    if (int rc = build_sources_fixed(d, src, nsrc, B, ents, nents, first, nfirst)) return rc;
+    const WsLayout Lw = ws_layout<R, B>(nblk, 1, (size_t)nents);
+    if (Lw.total > FMM_NOALLOC_SCRATCH_BYTES) {
+        char msg[200];
+        std::snprintf(msg, sizeof(msg),
+                      "fmm_solve_noalloc: the grid needs %zu bytes of device workspace, the static "
+                      "scratch holds %zu",
+                      Lw.total, (size_t)FMM_NOALLOC_SCRATCH_BYTES);
+        return fail(FMM_ENOMEM, msg);
+    }
+    Device dev;
+    if (int rc = device_info(dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    void *base = nullptr;
+    if (int rc = scratch_address(dev.id, &base)) return rc;
+    KParams<R> kp{};
+    ws_bind<R>(kp, (char *)base, Lw);
+    LaunchIn in{&d, 1, nblk, ents, nents, (SrcEntry *)((char *)base + Lw.off[kWsSrc]), first, nfirst, &o};
+    LaunchEvents ev;  // no events: creating them is not part of this path
+    if (int rc = launch_solve<R, B, W>(kp, in, dev, st, ev, ctl_out, grid_out)) return rc;
+    return map_device_error(ctl_out.abort);
+}
+
+using NoallocFn = int (*)(const ProbDesc &, const fmm_source *, int32_t, const fmm_options &,
+                          hipStream_t, Ctl &, int &);
+
+template <typename R>
+NoallocFn pick_noalloc(int B, int W)
+{
+#define FMM_CASE(b, w) \
+    if (B == b && W == w) return &run_solve_noalloc<R, b, w>;
+    FMM_CASE(4, 1)
+    FMM_CASE(4, 2)
+    FMM_CASE(4, 4)
+    FMM_CASE(8, 1)
+    FMM_CASE(8, 2)
+    FMM_CASE(8, 4)
+    FMM_CASE(16, 1)
+    FMM_CASE(16, 2)
+    FMM_CASE(16, 4)
+#undef FMM_CASE
+    return nullptr;
+}
+
 using RunFn = int (*)(std::vector<Prob> &, const fmm_options &, hipStream_t, RunOut &);
 
 template <typename R>
@@ -724,6 +846,60 @@ int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const
         return fail(FMM_EHIP, std::string("fmm_solve: ") + e.what());
     } catch (...) {
         return fail(FMM_EHIP, "fmm_solve: unknown exception");
+    }
+}
+
+int fmm_solve_noalloc(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
+                      const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
+                      void *hip_stream, const fmm_options *opt, fmm_stats *stats)
+{
+    try {
+        fmm_options o;
+        fmm_options_default(&o);
+        if (opt) o = *opt;
+        if (int rc = check_options(o)) return rc;
+        if (int rc = validate_problem(nx, ny, nz, h, F_dev, psi_dev, src, nsrc, block, stride, "noalloc"))
+            return rc;
+        if (o.stride_mode == FMM_STRIDE_LEARNED && !std::isfinite(stride))
+            return fail(FMM_EINVAL, "fmm_solve_noalloc: learned stride needs a finite base stride");
+        if (nsrc > kNoallocMaxSources)
+            return fail(FMM_EINVAL, "fmm_solve_noalloc: at most 256 sources");
+        const int W = o.waves_per_block <= 0 ? 1 : o.waves_per_block;
+        if (W != 1 && W != 2 && W != 4) return fail(FMM_EINVAL, "waves_per_block must be 1, 2 or 4");
+        NoallocFn fn = nullptr;
+        if (dtype == FMM_F32) fn = pick_noalloc<float>(block, W);
+        else if (dtype == FMM_F64) fn = pick_noalloc<double>(block, W);
+        else return fail(FMM_EINVAL, "dtype must be FMM_F32 or FMM_F64");
+        if (!fn) return fail(FMM_ENOTSUP, "unsupported block / waves combination");
+        ProbDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.F = F_dev;
+        d.psi = psi_dev;
+        d.nx = (int32_t)nx;
+        d.ny = (int32_t)ny;
+        d.nz = (int32_t)nz;
+        d.h = h;
+        d.stride = stride;
+        d.width = o.width;
+        Ctl ctl;
+        std::memset(&ctl, 0, sizeof(ctl));
+        int grid = 0;
+        const int rc = fn(d, src, nsrc, o, (hipStream_t)hip_stream, ctl, grid);
+        if (stats && (rc == 0 || rc == FMM_ENOCONV)) {
+            std::memset(stats, 0, sizeof(*stats));
+            stats->restarts = ctl.restarts;
+            stats->pops = (int64_t)ctl.pops;
+            stats->march_calls = (int64_t)ctl.march_calls;
+            stats->exchange_calls = (int64_t)ctl.exchange_calls;
+            stats->tile_loads = (int64_t)ctl.tile_loads;
+            stats->final_bound = ctl.final_bound;
+            stats->grid = grid;
+            stats->block = block;
+            stats->waves_per_block = W;
+        }
+        return rc;
+    } catch (...) {
+        return fail(FMM_EHIP, "fmm_solve_noalloc: unexpected exception");
     }
 }
 

@@ -95,6 +95,9 @@ def load():
     lib.fmm_solve.argtypes = [i64, i64, i64, dbl, i32, vp, C.POINTER(Source), i32, i32, dbl, vp,
                               vp, C.POINTER(Options), C.POINTER(Stats)]
     lib.fmm_solve.restype = C.c_int
+    lib.fmm_solve_noalloc.argtypes = [i64, i64, i64, dbl, i32, vp, C.POINTER(Source), i32, i32,
+                                      dbl, vp, vp, C.POINTER(Options), C.POINTER(Stats)]
+    lib.fmm_solve_noalloc.restype = C.c_int
     lib.fmm_solve_batched.argtypes = [i32, C.POINTER(Problem), i32, i32, C.POINTER(Options), vp,
                                       C.POINTER(Stats)]
     lib.fmm_solve_batched.restype = C.c_int
@@ -208,6 +211,30 @@ def solve(F, h: float, sources: Sequence, block: int = 16, stride: Optional[floa
     rc = lib.fmm_solve(nx, ny, nz, float(h), _dtype_code(F), F.data_ptr(), src, len(sources),
                        int(block), stride, out.data_ptr(), _stream(), C.byref(o), C.byref(st))
     _check(rc, "fmm_solve")
+    return (out, st.as_dict()) if with_stats else out
+
+
+def solve_noalloc(F, h: float, sources: Sequence, out, block: int = 16,
+                  stride: Optional[float] = None, with_stats: bool = False, **opts):
+    """solve() through fmm_solve_noalloc: the library allocates no device memory (its
+    workspace is a fixed static array per GPU).  `out` is required (same shape and dtype
+    as F); grids whose workspace exceeds the array raise FmmError (FMM_ENOMEM)."""
+    lib = load()
+    _check_tensor(F, "F")
+    if F.dim() != 3:
+        raise ValueError("F must have shape (nz, ny, nx)")
+    nz, ny, nx = F.shape
+    _check_tensor(out, "out")
+    if out.dtype != F.dtype or out.shape != F.shape:
+        raise ValueError("out must match F in shape and dtype")
+    stride = 2.0 * h if stride is None else float(stride)
+    o = make_options(**opts)
+    src = _sources(sources)
+    st = Stats()
+    rc = lib.fmm_solve_noalloc(nx, ny, nz, float(h), _dtype_code(F), F.data_ptr(), src,
+                               len(sources), int(block), stride, out.data_ptr(), _stream(),
+                               C.byref(o), C.byref(st))
+    _check(rc, "fmm_solve_noalloc")
     return (out, st.as_dict()) if with_stats else out
 
 
