@@ -16,7 +16,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# FMM_SANITIZE=1 loads the AddressSanitizer / UBSan builds (build.py --sanitize)
+_SAN = os.environ.get("FMM_SANITIZE") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if _SAN else "liboracle.so")
 _lib = None
 
 ORC_EINVAL, ORC_ENOMEM, ORC_ENOCONV = -1, -2, -3
@@ -33,7 +35,7 @@ def _load():
         return _lib
     if not os.path.exists(_LIB_PATH):
         from . import build as _b
-        _b.build()
+        _b.build(sanitize=_SAN)
     lib = C.CDLL(_LIB_PATH)
     for sfx in ("f64", "f32"):
         f = getattr(lib, f"orc_fmm_{sfx}")
@@ -198,10 +200,10 @@ def _load_par():
     global _par
     if _par is not None:
         return _par
-    path = os.path.join(_HERE, "libcpu_parallel.so")
+    path = os.path.join(_HERE, "libcpu_parallel_san.so" if _SAN else "libcpu_parallel.so")
     if not os.path.exists(path):
         from . import build as _b
-        _b.build()
+        _b.build(sanitize=_SAN)
     lib = C.CDLL(path)
     for sfx in ("f64", "f32"):
         f = getattr(lib, f"cpu_block_fmm_par_{sfx}")

@@ -14,23 +14,37 @@ PAR_LIB = os.path.join(HERE, "libcpu_parallel.so")  # the paper's OpenMP block s
 PAR_SOURCES = [os.path.join(HERE, "cpu_parallel.c")]
 
 
-def build(verbose: bool = False) -> str:
+# Sanitizer builds (AddressSanitizer and UndefinedBehaviorSanitizer, host code only):
+# liboracle_san.so and libcpu_parallel_san.so, loaded instead of the plain ones when
+# FMM_SANITIZE=1 (with libasan preloaded into the interpreter).
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
+
+
+def lib_path(name: str, sanitize: bool) -> str:
+    return os.path.join(HERE, name.replace(".so", "_san.so") if sanitize else name)
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    lib = lib_path("liboracle.so", sanitize)
+    par_lib = lib_path("libcpu_parallel.so", sanitize)
+    extra = SAN_FLAGS if sanitize else []
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter",
-           "-o", LIB + ".tmp"] + [s for s in SOURCES if os.path.exists(s)] + ["-lm"]
+           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter"] + extra + [
+           "-o", lib + ".tmp"] + [s for s in SOURCES if os.path.exists(s)] + ["-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
     par = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter", "-Wno-unused-function",
-           "-o", PAR_LIB + ".tmp"] + PAR_SOURCES + ["-lm"]
+           "-fno-fast-math", "-Wall", "-Wextra", "-Wno-unused-parameter", "-Wno-unused-function"
+           ] + extra + ["-o", par_lib + ".tmp"] + PAR_SOURCES + ["-lm"]
     if verbose:
         print(" ".join(par), flush=True)
     subprocess.run(par, check=True)
-    os.replace(PAR_LIB + ".tmp", PAR_LIB)
-    return LIB
+    os.replace(par_lib + ".tmp", par_lib)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv)
