@@ -18,8 +18,11 @@ Prints ONE JSON line.  Besides the contract fields it carries
   cpu_baseline  the CPU oracle (single-heap FMM, one thread) timed on a bounded
                 sample of the same workload on this host
   extra         restarts, pops, pops/s, device times, launch shape; for the
-                default workload also the same solve with the learned stride
-                (when trained weights are present) and with 8^3 blocks
+                default workload also the other configurations, each timed once
+                after a warm-up: the learned stride and 8^3 blocks on the same
+                field, the paper's case 1 at 1024^3 in FP64, the 64^3 and 256^3
+                workloads, the 512-solve batch against 512 sequential solves, and a
+                held-out 512^3 field with the learned stride against fixed ones
 """
 import argparse
 import hashlib
@@ -167,6 +170,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned-stride and 8^3-block solves of the default workload")
+    ap.add_argument("--per-problem-restarts", action="store_true",
+                    help="batched_512: time the launch in which every solve restarts on its own")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -265,10 +270,165 @@ def run_single(args, torch, fmm):
         out["extra"]["block8"] = {"Mpts_per_s": round(npts / bwall / 1e6, 3),
                                   "pops": bs[-1]["pops"], "grid": bs[-1]["grid"],
                                   "max_abs_diff_vs_block16": diff, "within_fp32_bar": diff <= tol}
-        del out8, fixed
+        del out8, fixed, psi, F
+        torch.cuda.empty_cache()
+        out["extra"]["fp64_1024_paper_case1"] = leg_fp64_1024(torch, fmm)
+        out["extra"]["small_workloads"] = leg_small(torch, fmm)
+        out["extra"]["batched_512"] = leg_batched(torch, fmm)
+        out["extra"]["heldout_512_learned_stride"] = leg_heldout(torch, fmm)
     if not args.no_cpu_baseline:
         out["cpu_baseline"], out["extra"]["cpu_parallel_block_solver"] = cpu_baseline(p, args.workload)
     return out
+
+
+def _once(fn, label):
+    """One warm-up, then one timed call on a drained device: (stats, seconds)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] {label}: {dt * 1e3:.1f} ms, {st.get('restarts')} restarts, "
+          f"{st.get('pops')} pops", file=sys.stderr, flush=True)
+    return st, dt
+
+
+def leg_fp64_1024(torch, fmm):
+    """The paper's case 1 (F = 1, source at the centre of the cell-centred unit cube) at
+    its finest grid, 1024^3, in FP64, with 16^3 and 8^3 blocks, stride 2h."""
+    n = 1024
+    h = 1.0 / n
+    F = torch.ones((n, n, n), dtype=torch.float64, device="cuda")
+    src = [(n // 2, n // 2, n // 2, 0.0)]
+    res = {"grid": [n, n, n], "stride_h": 2.0, "dtype": "f64"}
+    outs = {}
+    for b in (16, 8):
+        psi = torch.empty_like(F)
+        st, dt = _once(lambda: fmm.solve(F, h, src, block=b, stride=2 * h, out=psi,
+                                         with_stats=True)[1], f"fp64 1024^3 case 1 block {b}")
+        res[f"block{b}"] = {"Mpts_per_s": round(n ** 3 / dt / 1e6, 3), "restarts": st["restarts"],
+                            "pops": st["pops"], "loop_ms": round(st["loop_ms"], 3)}
+        outs[b] = psi
+    # multi-block solutions agree to rounding (Sec. 3.2): block 8 against block 16
+    res["max_abs_diff_block8_vs_block16"] = float((outs[8] - outs[16]).abs().max())
+    res["source_value"] = float(outs[16][n // 2, n // 2, n // 2])
+    del outs, F
+    torch.cuda.empty_cache()
+    return res
+
+
+def leg_small(torch, fmm):
+    """The 64^3 point-source workload (FP64, 8^3 blocks) and the 256^3 sine workload (FP32
+    and FP64, 16^3 blocks), each the mean of 5 timed solves after 2 warm-ups."""
+    import numpy as np
+    from paper_1811_00009_amd import inputs
+    res = {}
+    cases = (("point_64_f64_b8", inputs.smooth_point(64), np.float64, 8),
+             ("sine_256_f32_b16", inputs.smooth_sine(256, dtype=np.float32), np.float32, 16),
+             ("sine_256_f64_b16", inputs.smooth_sine(256, dtype=np.float64), np.float64, 16))
+    for name, p, dt_, b in cases:
+        F = torch.from_numpy(np.ascontiguousarray(p.F, dtype=dt_)).cuda()
+        psi = torch.empty_like(F)
+        for _ in range(2):
+            fmm.solve(F, p.h, p.sources, block=b, stride=2 * p.h, out=psi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            st = fmm.solve(F, p.h, p.sources, block=b, stride=2 * p.h, out=psi, with_stats=True)[1]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        res[name] = {"Mpts_per_s": round(F.numel() / dt / 1e6, 3), "ms": round(dt * 1e3, 3),
+                     "restarts": st["restarts"], "pops": st["pops"]}
+        print(f"[bench] {name}: {dt * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    return res
+
+
+def leg_batched(torch, fmm, nsolve=512):
+    """512 solves of uneven sizes in one persistent launch (block and waves from the
+    autotuner) against the same solves as 512 plain launches; psi identical, and two of
+    the solves against the single-heap oracle."""
+    import numpy as np
+    import oracle
+    from paper_1811_00009_amd import inputs
+    t0 = time.perf_counter()
+    probs = [inputs.batched_problem_device(s, torch) for s in range(nsolve)]
+    torch.cuda.synchronize()
+    npts = sum(int(p.F.numel()) for p in probs)
+    tune = fmm.autotune([(p.F, p.h, p.sources) for p in probs[::16]])
+    B, W = tune["block"], tune["waves_per_block"]
+    print(f"[bench] batched_512: {npts} points, built and tuned in {time.perf_counter() - t0:.1f} s"
+          f" (block {B}, waves {W})", file=sys.stderr, flush=True)
+    batch = [(p.F, p.h, p.sources) for p in probs]
+    outs = [torch.empty_like(p.F) for p in probs]
+    st, dt = _once(lambda: fmm.solve_batched(batch, block=B, waves_per_block=W, outs=outs,
+                                             with_stats=True)[1][0], "batched_512 one launch")
+    seq_out = [torch.empty_like(p.F) for p in probs]
+    for p, o in zip(probs[:4], seq_out):
+        fmm.solve(p.F, p.h, p.sources, block=B, waves_per_block=W, out=o)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for p, o in zip(probs, seq_out):
+        fmm.solve(p.F, p.h, p.sources, block=B, waves_per_block=W, out=o)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    same = all(torch.equal(a, b) for a, b in zip(outs, seq_out))
+    other = _batched_other_mode(torch, fmm, batch, B, W, True, seq_out, npts)
+    # two of the batch's solves against the single-heap oracle on the same speed values
+    sides = [int(p.F.shape[0]) for p in probs]
+    pick = sorted(range(nsolve), key=lambda s: sides[s])[:2]
+    checks = []
+    for s in pick:
+        Fh = probs[s].F.cpu().numpy()
+        ref32 = oracle.fmm(Fh, probs[s].h, probs[s].sources, dtype=np.float32)
+        ref64 = oracle.fmm(Fh.astype(np.float64), probs[s].h, probs[s].sources)
+        got = outs[s].cpu().numpy()
+        checks.append({"solve": s, "side": sides[s],
+                       "max_abs_diff_vs_fp32_oracle": float(np.max(np.abs(got - ref32))),
+                       "max_abs_diff_vs_fp64_oracle": float(np.max(np.abs(got - ref64))),
+                       "bar_1e-5_max_psi": float(1e-5 * ref32.max())})
+    res = {"solves": nsolve, "points": npts, "block": B, "waves_per_block": W,
+           "Mpts_per_s": round(npts / dt / 1e6, 3), "ms": round(dt * 1e3, 3),
+           "sequential_Mpts_per_s": round(npts / seq / 1e6, 3),
+           "batched_over_sequential": round(seq / dt, 3), "identical_to_sequential": same,
+           "per_problem_restarts": other, "oracle_checks": checks}
+    del probs, outs, seq_out, batch
+    torch.cuda.empty_cache()
+    return res
+
+
+def leg_heldout(torch, fmm):
+    """A held-out 512^3 coarse-cell field (the stride network never saw it): the learned
+    stride against the fixed strides 1h, 2h and 4h (multipliers 1/2, 1, 2 of 2h)."""
+    from paper_1811_00009_amd import inputs
+    blob = load_weights(torch)
+    if blob is None:
+        return None
+    n = 512
+    p = inputs.stride_field((50, 0), n, materialize=False)
+    F = inputs.expand_cells_device(p.meta["V"], n, torch)
+    psi = torch.empty_like(F)
+    res = {"field": "SeedSequence([50, 0]), 512^3, 64^3 coarse cells", "block": 16}
+    fixed = {}
+    for m in (0.5, 1.0, 2.0):
+        st, dt = _once(lambda: fmm.solve(F, p.h, p.sources, block=16, stride=m * 2 * p.h,
+                                         out=psi, with_stats=True)[1], f"heldout fixed {m}x2h")
+        fixed[m] = dt
+        res[f"fixed_{m}x2h_Mpts_per_s"] = round(n ** 3 / dt / 1e6, 3)
+    ref = psi.clone()
+    st, dt = _once(lambda: fmm.solve(F, p.h, p.sources, block=16, stride=2 * p.h, out=psi,
+                                     with_stats=True, stride_mode="learned",
+                                     mlp_weights=blob)[1], "heldout learned")
+    best = min(fixed.values())
+    res.update({"learned_Mpts_per_s": round(n ** 3 / dt / 1e6, 3),
+                "learned_restarts": st["restarts"],
+                "learned_over_best_fixed": round(best / dt, 4),
+                "learned_over_fixed_2h": round(fixed[1.0] / dt, 4),
+                "max_abs_diff_learned_vs_fixed_4h": float((psi - ref).abs().max())})
+    del F, psi, ref
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_batched(args, torch, fmm):
@@ -290,9 +450,11 @@ def run_batched(args, torch, fmm):
     batch = [(p.F, p.h, p.sources) for p in probs]
     outs = [torch.empty_like(p.F) for p in probs]
 
+    pp = bool(args.per_problem_restarts)
+
     def step():
         per = fmm.solve_batched(batch, block=B, waves_per_block=W, outs=outs,
-                                with_stats=True)[1]
+                                with_stats=True, per_problem_restarts=pp)[1]
         st = dict(per[0])  # times and launch shape are the launch's, the same in every row
         st["pops"] = sum(s["pops"] for s in per)
         st["restarts"] = max(s["restarts"] for s in per)
@@ -315,10 +477,11 @@ def run_batched(args, torch, fmm):
     same = all(torch.equal(a, b) for a, b in zip(outs, seq_out))
     print(f"[bench] sequential: {seq * 1e3:.1f} ms for {nsolve} launches; identical: {same}",
           file=sys.stderr, flush=True)
+    other = _batched_other_mode(torch, fmm, batch, B, W, not pp, seq_out, npts)
     out = contract(args, value, ms_per_step, "f32",
                    {"workload": "batched_512", "solves": nsolve, "points": npts,
                     "sides": "uniform over {32, 48, ..., 192}", "block": B, "waves_per_block": W,
-                    "stride_h": 2.0, "stride_mode": "fixed",
+                    "stride_h": 2.0, "stride_mode": "fixed", "per_problem_restarts": pp,
                     "tuned_on": "fields 0, 16, ..., 496"})
     out["roofline"] = roofline("f32", npts, loop_ms, "batched_512", out["config"])
     out["extra"] = {"pops": stats[-1]["pops"], "max_restarts": stats[-1]["restarts"],
@@ -326,10 +489,28 @@ def run_batched(args, torch, fmm):
                     "sequential_Mpts_per_s": round(npts / seq / 1e6, 3),
                     "batched_over_sequential": round(seq / (wall / args.steps), 3),
                     "identical_to_sequential": same, "loop_ms": round(loop_ms, 3),
-                    "grid": stats[-1]["grid"], "kernel_hash": kernel_source_hash()}
+                    "grid": stats[-1]["grid"], "kernel_hash": kernel_source_hash(),
+                    "other_mode": other}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batched()
     return out
+
+
+def _batched_other_mode(torch, fmm, batch, B, W, per_problem, ref_outs, npts):
+    """The same batch once more with the other restart discipline (one warm-up, one timed
+    launch): all solves behind one grid barrier per step, or each solve restarting on its
+    own.  psi must not change."""
+    outs = [torch.empty_like(b[0]) for b in batch]
+    label = "per-problem restarts" if per_problem else "shared restarts"
+    st, dt = _once(lambda: fmm.solve_batched(batch, block=B, waves_per_block=W, outs=outs,
+                                             with_stats=True,
+                                             per_problem_restarts=per_problem)[1][0],
+                   f"batched, {label}")
+    same = all(torch.equal(a, b) for a, b in zip(outs, ref_outs))
+    del outs
+    return {"per_problem_restarts": per_problem, "Mpts_per_s": round(npts / dt / 1e6, 3),
+            "ms": round(dt * 1e3, 3), "loop_ms": round(st["loop_ms"], 3),
+            "identical_to_sequential": same}
 
 
 def cpu_baseline_batched(seconds_target=12.0):

@@ -55,10 +55,15 @@ typedef enum { FMM_F32 = 0, FMM_F64 = 1 } fmm_dtype;
 /* Stride policy of the restart driver. */
 typedef enum {
     FMM_STRIDE_FIXED = 0,   /* bound_r = min(r * stride, width)            (Alg. 6) */
-    FMM_STRIDE_LEARNED = 1  /* bound_r = bound_{r-1} + m_r * stride, m_r from the
+    FMM_STRIDE_LEARNED = 1, /* bound_r = bound_{r-1} + m_r * stride, m_r from the
                                stride network evaluated on the device at the end
                                of restart r-1; falls back to m_r = 1 when the
                                weights are absent or the output is not finite */
+    FMM_STRIDE_SCHEDULE = 2 /* a given bound sequence (fmm_options.bounds):
+                               bound_r = min(bounds[r-1], width) for r <= nbounds, then
+                               min(bounds[nbounds-1] + (r - nbounds) * stride, width);
+                               any non-decreasing sequence gives the same psi, only the
+                               restarts differ (used to replay and explore strides) */
 } fmm_stride_mode;
 
 /* Launch strategy of the restart loop. */
@@ -89,6 +94,13 @@ typedef struct {
     int32_t band_lds_cap;     /* diagnostic: band slots kept in LDS while a block marches, a
                                  multiple of 512; 0 = the default (1024); slots beyond it are
                                  kept in device memory                                         */
+    const double *bounds;     /* FMM_STRIDE_SCHEDULE: host array of nbounds finite, positive,
+                                 non-decreasing bounds, copied during the call; else unused    */
+    int32_t nbounds;          /* 1 .. 2^24 for FMM_STRIDE_SCHEDULE                            */
+    int32_t per_problem_restarts; /* 1: the problems of a batch restart on their own (no
+                                 barrier shared between problems; fixed stride, persistent
+                                 launch, at most 2^20 - 2^17 blocks per problem); 0 (default):
+                                 one restart sequence for the whole batch                     */
 } fmm_options;
 
 /* Solve statistics (host struct, filled after the call). */
@@ -136,7 +148,9 @@ void fmm_options_default(fmm_options *opt);
  *                obstacle where the quadratic is never solved (paper Sec. 3.3)
  *   src, nsrc    host array of nsrc >= 1 points of Gamma, each inside the grid,
  *                psi0 >= 0 finite; a repeated point keeps the smallest psi0
- *   block        block edge B: 4, 8 or 16 (the paper's dimBlock)
+ *   block        block edge B: 4, 8, 16 or 32 (the paper's dimBlock); 32^3 blocks take
+ *                one wave per block and march their tile in device memory (a padded
+ *                FP32 tile does not fit in LDS), FMM_ENOTSUP with more waves
  *   stride       restart stride (> 0, +inf allowed = the non-restarted block
  *                method of Sec. 2.3)
  *   psi_dev      output, nx*ny*nz elements; points never reached are +inf
@@ -147,6 +161,30 @@ void fmm_options_default(fmm_options *opt);
 int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
               const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
               void *hip_stream, const fmm_options *opt, fmm_stats *stats);
+
+/*
+ * Stop and resume (for exploring stride schedules from a common state, as the stride
+ * network's training labels do).  A solve given fmm_options.max_restarts stops after that
+ * restart with FMM_ENOCONV, its state (tiles, bands, flags, lists) left in the library's
+ * workspace on this device.  fmm_solve_resume continues it with restart from_restart + 1,
+ * where from_restart is the restart it stopped after (stats->restarts of that call):
+ *  * the arguments name the same problem as the stopped solve (grid, h, dtype, F, sources,
+ *    block, waves per block), FMM_EINVAL otherwise; psi_dev receives the result (or, when
+ *    it stops again, the values so far); stride_mode FIXED or SCHEDULE (at most 65536
+ *    bounds), persistent launch only;
+ *  * with a bound schedule, restart r takes bounds[r - 1]: a schedule that repeats the
+ *    stopped solve's bounds up to from_restart continues it exactly as one solve with the
+ *    whole schedule would; stats count the resumed restarts' pops and calls only.
+ * fmm_workspace_save copies that state (*bytes_out bytes; dst_dev NULL = size query) into
+ * a caller device buffer; fmm_workspace_restore copies it back, so several continuations
+ * can start from one state.  Both are synchronous on hip_stream.  Another solve on the
+ * device replaces the state.
+ */
+int fmm_solve_resume(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
+                     const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
+                     void *hip_stream, const fmm_options *opt, int64_t from_restart, fmm_stats *stats);
+int fmm_workspace_save(void *dst_dev, size_t cap_bytes, size_t *bytes_out, void *hip_stream);
+int fmm_workspace_restore(const void *src_dev, size_t bytes, void *hip_stream);
 
 /*
  * fmm_solve without any device allocation, for callers that cannot allocate: code
@@ -183,11 +221,15 @@ typedef struct {
 } fmm_problem;
 
 /*
- * Solve nsolves independent problems in ONE persistent launch: the blocks of
- * every problem share the march and exchange lists of Alg. 6, and each problem
- * keeps its own bound (r * its stride).  block and waves_per_block apply to the
- * whole batch (fmm_autotune chooses them).  per_solve_stats is nullable or an
- * array of nsolves; restarts are per problem, elapsed_ms is the batch time.
+ * Solve nsolves independent problems in ONE launch.  By default the blocks of every
+ * problem share the march and exchange lists of Alg. 6 and one restart index, and each
+ * problem keeps its own bound (r * its stride).  With opt->per_problem_restarts every
+ * problem runs its own restarts: work-groups take work items (blocks) of whichever
+ * problem has some, and a problem moves to its next step when its own items are done,
+ * with no barrier between problems.  Either way each problem's psi and counts are those
+ * of its own fmm_solve.  block and waves_per_block apply to the whole batch
+ * (fmm_autotune chooses them).  per_solve_stats is nullable or an array of nsolves;
+ * restarts are per problem, elapsed_ms is the batch time.
  */
 int fmm_solve_batched(int32_t nsolves, const fmm_problem *problems, int32_t dtype, int32_t block,
                       const fmm_options *opt, void *hip_stream, fmm_stats *per_solve_stats);
@@ -201,7 +243,8 @@ typedef struct {
 
 /*
  * Choose block edge and waves per block for a batch by timing every supported
- * pair (block in {8, 16} dividing all sides, waves in {1, 2, 4}) on the given
+ * pair (block in {8, 16, 32} dividing all sides, waves in {1, 2, 4}, one wave for
+ * 32) on the given
  * sample problems, once each after one warm-up.  Results are cached in memory
  * and, when cache_path is not NULL, in a small text file keyed by device name,
  * dtype and a size bin, so a later call with the same key does not time again.
@@ -258,15 +301,23 @@ int fmm_selftest_wave_min(const uint32_t *in_dev, uint32_t *out_dev, int32_t nwa
 /* Locate_Min (Alg. 4: the band point of least psi, ties to the lower tile index) of a
    march by one wave, on a given band: psi_dev holds the (B+2)^3 tile values of one block
    (dtype; entry 0, the tile corner, is never a band point and reads as +inf) and band_dev
-   n distinct tile indices in [1, (B+2)^3), 1 <= n < (B+2)^3.  The first `cap` slots (0 or
-   a multiple of 512; 0 = as many as a march keeps there) are staged in LDS as in a march,
-   the rest are read from device memory.  Writes the picked value to val_out_dev[0] (dtype) and its tile
+   n distinct tile indices in [1, (B+2)^3), 1 <= n < (B+2)^3.  The tile is staged in LDS
+   and the band held as a one-wave march holds it: the first `cap` slots (0 or a multiple
+   of 512; 0 = as many as a march keeps there: 1024 for B = 16, 512 for 8, 256 for 4) in
+   registers, the rest read from device memory.  Writes the picked value to val_out_dev[0] (dtype) and its tile
    index and band slot to idx_out_dev[0], idx_out_dev[1].  Synchronous on hip_stream;
    allocates a padded copy of the band.  FMM_EINVAL for null pointers, an unsupported
    dtype or block size (4, 8, 16), n out of range or a bad cap. */
 int fmm_selftest_band_argmin(int dtype, int32_t block, const void *psi_dev,
                              const uint16_t *band_dev, int32_t n, int32_t cap,
                              void *val_out_dev, int32_t *idx_out_dev, void *hip_stream);
+
+/* Frees the device memory and events the library holds on every device it has run on
+   (workspace arenas, stride-network scratch, cached tunings); later calls allocate again.
+   The static array of fmm_solve_noalloc stays with the loaded module.  The Python binding
+   calls it when the interpreter exits, so that the HIP runtime's own teardown finds
+   nothing of the library's left.  Must not overlap a call in flight. */
+int fmm_release(void);
 
 const char *fmm_strerror(int code);
 const char *fmm_last_error_detail(void);

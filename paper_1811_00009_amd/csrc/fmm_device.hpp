@@ -136,9 +136,30 @@ struct Ctl {
                                       // (2^20 fixed point), unused; by parity of the list
     long long restarts;
     double final_bound;
+    // batches with restarts of their own per problem (k_batched): the ready queue of
+    // problem tokens and the count of problems still running
+    alignas(128) unsigned long long rq_head;
+    alignas(128) unsigned long long rq_tail;
+    alignas(128) int remaining;
     struct alignas(128) BarGroup {
         unsigned count;
     } bar_grp[kBarGroups];            // grid barrier arrivals, work-group w in group w % 64
+};
+
+// One problem of a batch whose restarts are its own: the phase it is in and that phase's
+// work items, claimed one at a time by the work-groups holding one of its tokens.  word =
+// phase << 40 | items << 20 | claims; phase 2 (r - 1) is the marching step of restart r,
+// phase 2 (r - 1) + 1 its exchanging step.  The list counters are the problem's own, by
+// restart parity, as the launch-wide ones of Ctl.
+struct alignas(128) SolveState {
+    unsigned long long word;
+    int done;         // items of the current phase finished
+    int r;            // restarts begun (the last one when finished)
+    int n_list[2];
+    int bin_n[2][4];
+    int x_n[2];
+    int finished;
+    int queued;       // this problem's tokens in the ready queue (or about to be put there)
 };
 
 // Device-side error codes (stored in Ctl::abort; mapped to fmm.h codes by the host).
@@ -172,7 +193,14 @@ struct KParams {
     Ctl *ctl;
     const ProbDesc *prob;
     int32_t nprob;
-    int32_t stride_mode;   // 0 fixed, 1 learned
+    int32_t stride_mode;   // 0 fixed, 1 learned, 2 given bound sequence
+    const double *sched;   // stride_mode 2: bound of restart r is sched[r - 1] (r <= nsched)
+    int32_t nsched;
+    int64_t r0;            // restarts already done (a resumed solve continues with r0 + 1)
+    SolveState *solves;    // [nprob] batches with restarts of their own, else nullptr
+    unsigned long long *ring; // ready queue of problem tokens (seq << 32 | problem)
+    uint32_t ring_mask;    // ring size - 1 (a power of two)
+    int32_t tokens;        // tokens handed out per phase (work-groups that may share it)
     int64_t nblk;
     int64_t max_restarts;
     int64_t pop_cap;       // watchdog on pops of one march call
@@ -205,6 +233,19 @@ struct Geo {
     static constexpr int BANDC = BAND < 1024 ? BAND : 1024;
     static constexpr int TAGB = (T + 15) / 16 * 16;
     static constexpr bool RHS_LDS = B <= 8;
+    // 32^3 blocks: a padded FP32 tile alone is 157 KB, so the march works on the tile in
+    // device memory (one wave per block); the band's first slots stay in LDS
+    static constexpr bool TILE_LDS = B <= 16;
+};
+
+// Pointer to tile data: LDS for blocks up to 16^3, device memory beyond.
+template <typename T, bool IN_LDS>
+struct TilePtr {
+    typedef T *type;
+};
+template <typename T>
+struct TilePtr<T, true> {
+    typedef FMM_LDS T *type;
 };
 
 // Tile index of the e-th point of the six boundary layers of the interior, e in [0, 6 B^2):
@@ -221,10 +262,12 @@ __device__ __forceinline__ int face_point(int e)
 template <typename R, int B, int W>
 struct Lds {
     static constexpr int T = Geo<B>::T;
+    static constexpr size_t TILEB = Geo<B>::TILE_LDS ? sizeof(R) * T : 0;  // psi tile
+    static constexpr size_t TAGL = Geo<B>::TILE_LDS ? Geo<B>::TAGB : 0;     // tag tile
     static constexpr size_t psi_off = 0;
-    static constexpr size_t band_off = (psi_off + sizeof(R) * T + 15) / 16 * 16;
+    static constexpr size_t band_off = (psi_off + TILEB + 15) / 16 * 16;
     static constexpr size_t tag_off = band_off + 2 * Geo<B>::BANDC;
-    static constexpr size_t rhs_off = (tag_off + Geo<B>::TAGB + 15) / 16 * 16;
+    static constexpr size_t rhs_off = (tag_off + TAGL + 15) / 16 * 16;
     static constexpr size_t scr_off = rhs_off + (Geo<B>::RHS_LDS ? sizeof(R) * T : 0);
     static constexpr size_t bytes = scr_off + 16 * 8 + 64;
     // Waves per SIMD that the LDS footprint allows (160 KB per CU, 4 SIMDs).  The
@@ -233,7 +276,8 @@ struct Lds {
     // below that the march would spill.
     static constexpr int wgs_per_cu = (int)(163840 / (bytes + 128));
     static constexpr int lds_waves_per_simd = (wgs_per_cu * W + 3) / 4;
-    static constexpr int max_waves = (W == 1 && sizeof(R) == 4) ? 4 : 3;
+    // a march in device memory (32^3 blocks) is not bound by LDS: three waves per SIMD
+    static constexpr int max_waves = (W == 1 && sizeof(R) == 4 && Geo<B>::TILE_LDS) ? 4 : 3;
     static constexpr int waves_per_simd =
         lds_waves_per_simd > max_waves ? max_waves
                                        : (lds_waves_per_simd < 1 ? 1 : lds_waves_per_simd);
@@ -346,9 +390,9 @@ __device__ __forceinline__ bool val_eq(double a, double b) { return a == b; }
 // Minimum (value, key) over the 8 slots [c0 + 8 lane, c0 + 8 lane + 8) of one 512-slot chunk
 // of the band: two depth-3 trees, the minimum value first, then the smallest key
 // index << 16 | slot among the slots holding it.
-template <typename R>
+template <typename R, typename PsiP>
 __device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, const uint16_t *g_band,
-                                               int cap, const FMM_LDS R *s_psi, int n, int c0,
+                                               int cap, PsiP s_psi, int n, int c0,
                                                int lane, R &m_out, uint32_t &k_out FMM_CYC_PARAM)
 {
     const int base = c0 + lane * 8;
@@ -393,8 +437,8 @@ __device__ __forceinline__ void band_chunk_min(const FMM_LDS uint16_t *s_band, c
 
 // Minimum (value, key) over the S slots [S lane, S lane + S) of a band of n <= 64 S slots
 // held in LDS (S = 1, 2 or 4): the narrow form of band_chunk_min for small bands.
-template <typename R, int S>
-__device__ __forceinline__ void band_small_min(const FMM_LDS uint16_t *s_band, const FMM_LDS R *s_psi,
+template <typename R, int S, typename PsiP>
+__device__ __forceinline__ void band_small_min(const FMM_LDS uint16_t *s_band, PsiP s_psi,
                                                int n, int lane, R &m_out, uint32_t &k_out FMM_CYC_PARAM)
 {
     const int base = lane * S;
@@ -461,10 +505,10 @@ __device__ __forceinline__ void wave_pick(R bv, uint32_t bk, uint32_t &mh, uint3
 // IEEE bit patterns order like the values; the cross-lane step takes the
 // minimum value first (high then low word for FP64), then the minimum key
 // among the lanes holding it.  Returns the same result in every lane.
-template <typename R, int W>
+template <typename R, int W, typename PsiP>
 __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band,
                                                   const uint16_t *g_band, int cap,
-                                                  const FMM_LDS R *s_psi, int n FMM_CYC_PARAM)
+                                                  PsiP s_psi, int n FMM_CYC_PARAM)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const R inf = (R)INFINITY;
@@ -472,18 +516,18 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
     uint32_t bk = ~0u;
     if (W == 1 && n <= 256 && n <= cap) {
         // a small band in LDS: 1, 2 or 4 slots per lane (n is wave-uniform)
-        if (n <= 64) band_small_min<R, 1>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
-        else if (n <= 128) band_small_min<R, 2>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
-        else band_small_min<R, 4>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
+        if (n <= 64) band_small_min<R, 1, PsiP>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
+        else if (n <= 128) band_small_min<R, 2, PsiP>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
+        else band_small_min<R, 4, PsiP>(s_band, s_psi, n, lane, bv, bk FMM_CYC_ARG);
     } else {
         // the first chunk of each wave sets (bv, bk) directly; later chunks (bands of
         // more than 512 * W slots) are merged in
         int c0 = wid * 512;
-        if (c0 < n) band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk FMM_CYC_ARG);
+        if (c0 < n) band_chunk_min<R, PsiP>(s_band, g_band, cap, s_psi, n, c0, lane, bv, bk FMM_CYC_ARG);
         for (c0 += 512 * W; c0 < n; c0 += 512 * W) {
             R m;
             uint32_t km;
-            band_chunk_min<R>(s_band, g_band, cap, s_psi, n, c0, lane, m, km FMM_CYC_ARG);
+            band_chunk_min<R, PsiP>(s_band, g_band, cap, s_psi, n, c0, lane, m, km FMM_CYC_ARG);
             const bool better = (m < bv) | (val_eq(m, bv) & (km < bk));
             bv = better ? m : bv;
             bk = better ? km : bk;
@@ -601,6 +645,68 @@ __device__ __forceinline__ R quad_root(R c0, R c1, R c2, R rhs)
         }
     }
     return t;
+}
+
+// x / k for k = kk + 1 in {1, 2, 3}, rounded as the IEEE division.  FP32: the product
+// with c_k = 1, 1/2, RN(1/3), corrected by one fused multiply-add on the exact residual
+// x - k q0 (for k = 1 and 2 the product is already the quotient and the correction keeps
+// it; the sequence is checked against x / k over all non-negative binary32 values for
+// each k); x = inf stays inf.  FP64: the division itself.
+__device__ __forceinline__ float div_k(float x, int kk)
+{
+    const float c = kk == 0 ? 1.0f : (kk == 1 ? 0.5f : 0x1.555556p-2f);
+    const float kf = (float)(kk + 1);
+    const float q0 = x * c;
+    const float r = __builtin_fmaf(-kf, q0, x);
+    const float q1 = __builtin_fmaf(r, c, q0);
+    return q0 == INFINITY ? q0 : q1;
+}
+__device__ __forceinline__ double div_k(double x, int kk) { return x / (double)(kk + 1); }
+
+// Alg. 3 with a given number of candidates: the root of the quadratic of Eq. (2) over the
+// kk + 1 smallest of the three candidates (sorted here; +inf = absent), in the variable
+// shifted by the smallest, with the same operations as quad_root takes for that count.
+// Returns +inf when there is no candidate and leaves the sorted second and third
+// candidates in v1o, v2o.  With more candidates asked for than there are, the result is
+// not used (it may be NaN).
+template <typename R>
+__device__ __forceinline__ R quad_root_k(R c0, R c1, R c2, R rhs, int kk, R &v1o, R &v2o)
+{
+    R a = c0 < c1 ? c0 : c1;
+    R b = c0 < c1 ? c1 : c0;
+    R v0 = a < c2 ? a : c2;
+    R m = a < c2 ? c2 : a;
+    R v1 = b < m ? b : m;
+    R v2 = b < m ? m : b;
+    v1o = v1;
+    v2o = v2;
+    const R inf = (R)INFINITY;
+    if (!(v0 < inf)) return inf;
+    const R z = (R)0;
+    const R u1 = kk >= 1 ? v1 - v0 : z;
+    const R u2 = kk >= 2 ? v2 - v0 : z;
+    const R s1 = u1 + u2;
+    const R s2 = u1 * u1 + u2 * u2;
+    R disc = s1 * s1 - (R)(kk + 1) * (s2 - rhs);
+    if (disc < 0) disc = 0;
+    return v0 + div_k(s1 + root2(disc), kk);
+}
+
+// The value of lane 4 (lane / 4) + J in every lane of each quad (DPP quad permute).
+template <int J>
+__device__ __forceinline__ float quad_bcast(float x)
+{
+    constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false));
+}
+template <int J>
+__device__ __forceinline__ double quad_bcast(double x)
+{
+    constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6);
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, ctrl, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 } // namespace fmmdev

@@ -36,6 +36,7 @@ int fail(int code, const std::string &msg)
 
 // Used by the stride-network kernels to report through fmm_last_error_detail().
 void fmm_internal_set_detail(const std::string &msg) { g_detail = msg; }
+void fmm_internal_mlp_release();  // fmm_mlp.hip
 
 namespace {
 
@@ -75,13 +76,17 @@ int ensure(DevBuf &b, size_t bytes, const char *what)
 struct Workspace {
     DevBuf arena;
     hipEvent_t e0 = nullptr, e1 = nullptr, l0 = nullptr, l1 = nullptr;
+    // the last launch on this arena: its problem (grid, block, waves, dtype, sources) and
+    // the bytes of the arena it used, which fmm_solve_resume and the workspace copies check
+    std::string last_sig;
+    size_t last_total = 0;
 };
 
 // Buffers of one launch, each at a 256-byte aligned offset from one base address.
 enum WsBuf {
     kWsPsi, kWsTag, kWsBand, kWsBandN, kWsRhs, kWsBmin, kWsA, kWsCm, kWsBprob, kWsFmean,
     kWsLastpops, kWsList0, kWsList1, kWsXlist, kWsCtl, kWsProb, kWsSrc, kWsPlastr, kWsPpops,
-    kWsCount
+    kWsSched, kWsSolves, kWsRing, kWsCount
 };
 
 struct WsLayout {
@@ -90,7 +95,7 @@ struct WsLayout {
 };
 
 template <typename R, int B>
-WsLayout ws_layout(int64_t nblk, int32_t nprob, size_t nents)
+WsLayout ws_layout(int64_t nblk, int32_t nprob, size_t nents, size_t nsched = 0, size_t nring = 0)
 {
     constexpr size_t T = Geo<B>::T, BAND = Geo<B>::BAND, TAGB = Geo<B>::TAGB;
     const size_t nb = (size_t)nblk, np = (size_t)nprob;
@@ -114,6 +119,9 @@ WsLayout ws_layout(int64_t nblk, int32_t nprob, size_t nents)
     bytes[kWsSrc] = sizeof(SrcEntry) * std::max<size_t>(1, nents);
     bytes[kWsPlastr] = sizeof(int32_t) * np;
     bytes[kWsPpops] = sizeof(unsigned long long) * np;
+    bytes[kWsSched] = sizeof(double) * nsched;
+    bytes[kWsSolves] = nring ? sizeof(SolveState) * np : 0;  // per-problem restarts only
+    bytes[kWsRing] = sizeof(unsigned long long) * nring;
     WsLayout L;
     size_t at = 0;
     for (int k = 0; k < kWsCount; ++k) {
@@ -145,6 +153,9 @@ void ws_bind(KParams<R> &kp, char *base, const WsLayout &L)
     kp.prob = (const ProbDesc *)(base + L.off[kWsProb]);
     kp.prob_lastr = (int32_t *)(base + L.off[kWsPlastr]);
     kp.prob_pops = (unsigned long long *)(base + L.off[kWsPpops]);
+    kp.sched = (const double *)(base + L.off[kWsSched]);
+    kp.solves = (SolveState *)(base + L.off[kWsSolves]);
+    kp.ring = (unsigned long long *)(base + L.off[kWsRing]);
 }
 
 std::mutex g_mu;
@@ -185,8 +196,8 @@ int validate_problem(int64_t nx, int64_t ny, int64_t nz, double h, const void *F
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(FMM_EINVAL, who + ": grid dimensions must be > 0");
     if (!(h > 0) || !std::isfinite(h)) return fail(FMM_EINVAL, who + ": h must be finite and > 0");
     if (!(stride > 0)) return fail(FMM_EINVAL, who + ": stride must be > 0 (inf allowed)");
-    if (block != 4 && block != 8 && block != 16)
-        return fail(FMM_ENOTSUP, who + ": block must be 4, 8 or 16");
+    if (block != 4 && block != 8 && block != 16 && block != 32)
+        return fail(FMM_ENOTSUP, who + ": block must be 4, 8, 16 or 32");
     if (nx % block || ny % block || nz % block)
         return fail(FMM_EINVAL, who + ": every grid dimension must be divisible by block");
     if (nx * ny * nz > ((int64_t)1 << 34)) return fail(FMM_EINVAL, who + ": grid too large");
@@ -267,7 +278,7 @@ int map_device_error(int code)
     case 0: return 0;
     case kErrBadSpeed: return fail(FMM_EINVAL, "speed F has a negative, NaN or infinite value");
     case kErrPopCap: return fail(FMM_ENOCONV, "device watchdog: a march call exceeded the pop cap");
-    case kErrTimeout: return fail(FMM_ENOCONV, "device watchdog: a grid barrier wait timed out");
+    case kErrTimeout: return fail(FMM_ENOCONV, "device watchdog: a wait timed out (grid barrier or ready queue)");
     case kErrRestarts: return fail(FMM_ENOCONV, "restart cap reached");
     case kErrList: return fail(FMM_EHIP, "internal error: a work list overflowed or held a bad block index");
     default: return fail(FMM_EHIP, "unknown device error " + std::to_string(code));
@@ -319,7 +330,17 @@ struct LaunchIn {
     const int32_t *first;  // blocks of the first march list
     int32_t nfirst;
     const fmm_options *o;
+    int64_t resume_from = 0;  // > 0: the workspace holds the state after this restart
+    uint32_t nring = 0;       // > 0: a batch whose problems restart on their own (ring size)
 };
+
+// Tokens per phase of a problem with restarts of its own: enough for every work-group of
+// the launch to find work when few problems run, few enough to spread them over many.
+int batch_tokens(int64_t grid, int32_t nprob)
+{
+    const int64_t t = (2 * grid + nprob - 1) / nprob;
+    return (int)std::max<int64_t>(8, std::min<int64_t>(1024, t));
+}
 
 // Events around the launch (all null: no timing).
 struct LaunchEvents {
@@ -344,17 +365,28 @@ int launch_solve(KParams<R> &kp, const LaunchIn &in, const Device &dev, hipStrea
     hc.bin_n[1][0] = in.nfirst;
     hc.rmin[0] = hc.rmin[1] = ~0ull;
 
+    const bool resume = in.resume_from > 0;
     HIPCHK(hipMemcpyAsync((void *)kp.prob, in.descs, sizeof(ProbDesc) * in.nprob, hipMemcpyHostToDevice, st));
-    if (in.nents > 0)
-        HIPCHK(hipMemcpyAsync(in.ents_dev, in.ents, sizeof(SrcEntry) * in.nents, hipMemcpyHostToDevice, st));
-    if (in.nfirst > 0)
-        HIPCHK(hipMemcpyAsync(kp.list1, in.first, sizeof(int32_t) * in.nfirst, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(kp.ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    if (!resume) {
+        if (in.nents > 0)
+            HIPCHK(hipMemcpyAsync(in.ents_dev, in.ents, sizeof(SrcEntry) * in.nents, hipMemcpyHostToDevice, st));
+        if (in.nfirst > 0 && in.nring == 0)  // (per-problem restarts: segments, below)
+            HIPCHK(hipMemcpyAsync(kp.list1, in.first, sizeof(int32_t) * in.nfirst, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(kp.ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, st));
+    } else {
+        // the control block, lists and tiles are those the stopped solve left; its stop
+        // (the restart cap) and its pop and call counts are cleared
+        k_clear_words<<<1, 64, 0, st>>>((uint32_t *)&kp.ctl->abort, 1);
+        k_clear_words<<<1, 64, 0, st>>>((uint32_t *)&kp.ctl->pops, 8);
+    }
+    if (o.stride_mode == FMM_STRIDE_SCHEDULE)
+        HIPCHK(hipMemcpyAsync((void *)kp.sched, o.bounds, sizeof(double) * o.nbounds, hipMemcpyHostToDevice, st));
     k_clear_words<<<1, 256, 0, st>>>((uint32_t *)kp.prob_lastr, in.nprob);
     k_clear_words<<<1, 256, 0, st>>>((uint32_t *)kp.prob_pops, 2 * (int64_t)in.nprob);
 
     kp.nprob = in.nprob;
-    kp.stride_mode = o.stride_mode == FMM_STRIDE_LEARNED ? 1 : 0;
+    kp.stride_mode = o.stride_mode == FMM_STRIDE_LEARNED ? 1 : (o.stride_mode == FMM_STRIDE_SCHEDULE ? 2 : 0);
+    kp.nsched = kp.stride_mode == 2 ? o.nbounds : 0;
     kp.nblk = nblk;
     kp.max_restarts = o.max_restarts > 0 ? o.max_restarts : 10000000;
     kp.pop_cap = (int64_t)64 * Geo<B>::T;
@@ -362,22 +394,75 @@ int launch_solve(KParams<R> &kp, const LaunchIn &in, const Device &dev, hipStrea
     kp.mlp = (const float *)o.mlp_weights;
     kp.trace = o.trace_dev;
     kp.trace_cap = o.trace_dev ? o.trace_cap : 0;
-    kp.want_features = (kp.trace_cap > 0 || kp.stride_mode) ? 1 : 0;
+    kp.want_features = (kp.trace_cap > 0 || kp.stride_mode == 1) ? 1 : 0;
     kp.band_cap = o.band_lds_cap;
+    kp.r0 = in.resume_from;
 
     const size_t lds = L::bytes;
     if (ev.e0) HIPCHK(hipEventRecord(ev.e0, st));
-    k_fill_blkprob<R><<<(unsigned)std::min<int64_t>((nblk + 255) / 256, 4096), 256, 0, st>>>(
-        kp.blk_prob, kp.prob, in.nprob, nblk);
-    k_init<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
-    if (in.nents > 0)
-        k_sources<R, B><<<(unsigned)((in.nents + 127) / 128), 128, 0, st>>>(kp, in.ents_dev, in.nents);
+    if (!resume) {
+        k_fill_blkprob<R><<<(unsigned)std::min<int64_t>((nblk + 255) / 256, 4096), 256, 0, st>>>(
+            kp.blk_prob, kp.prob, in.nprob, nblk);
+        k_init<R, B><<<(unsigned)std::min<int64_t>(nblk, 65536), 256, 0, st>>>(kp);
+        if (in.nents > 0)
+            k_sources<R, B><<<(unsigned)((in.nents + 127) / 128), 128, 0, st>>>(kp, in.ents_dev, in.nents);
+    }
     HIPCHK(hipGetLastError());
 
     int per_cu = 0;
     int grid = 0;
-    if (ev.l0) HIPCHK(hipEventRecord(ev.l0, st));
-    if (o.launch_mode == FMM_LAUNCH_PERSISTENT) {
+    if (ev.l0 && in.nring == 0) HIPCHK(hipEventRecord(ev.l0, st));
+    if (in.nring > 0) {
+        // a batch whose problems restart on their own: states, first lists and tokens
+        auto kern = k_batched<R, B, W>;
+        HIPCHK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, lds));
+        if (per_cu <= 0) return fail(FMM_ENOTSUP, "batch kernel does not fit on a compute unit");
+        int64_t g = (int64_t)per_cu * dev.cus;
+        g = std::min<int64_t>(g, nblk);
+        if (o.grid_limit > 0) g = std::min<int64_t>(g, o.grid_limit);
+        grid = (int)std::max<int64_t>(g, 1);
+        kp.tokens = batch_tokens(grid, in.nprob);
+        kp.ring_mask = in.nring - 1;
+        if ((uint64_t)in.nprob * (uint64_t)kp.tokens > in.nring)
+            return fail(FMM_EHIP, "internal error: token ring too small");
+        std::vector<SolveState> sst(in.nprob);
+        std::vector<unsigned long long> ring(in.nring);
+        for (uint32_t k = 0; k < in.nring; ++k) ring[k] = (unsigned long long)k << 32;  // empty slots
+        uint32_t ntok = 0;
+        int32_t f = 0;
+        for (int32_t q = 0; q < in.nprob; ++q) {
+            SolveState &ss = sst[q];
+            std::memset(&ss, 0, sizeof(ss));
+            const int64_t b0 = in.descs[q].blk0, b1 = b0 + in.descs[q].nblk;
+            const int32_t f0 = f;
+            while (f < in.nfirst && in.first[f] < b1) ++f;
+            const int32_t cnt = f - f0;
+            if (cnt <= 0 || in.first[f0] < b0)
+                return fail(FMM_EHIP, "internal error: a batch problem without source blocks");
+            ss.word = (unsigned long long)cnt << 20;  // phase 0: restart 1's marching step
+            ss.r = 1;
+            ss.n_list[1] = cnt;
+            ss.bin_n[1][0] = cnt;
+            HIPCHK(hipMemcpyAsync(kp.list1 + b0, in.first + f0, sizeof(int32_t) * cnt,
+                                  hipMemcpyHostToDevice, st));
+            const int t = std::min<int32_t>(cnt, kp.tokens);
+            ss.queued = t;
+            for (int k = 0; k < t; ++k, ++ntok)
+                ring[ntok] = ((unsigned long long)(ntok + 1) << 32) | (uint32_t)q;
+        }
+        const unsigned long long head = 0, tail = ntok;
+        const int remaining = in.nprob;
+        HIPCHK(hipMemcpyAsync(&kp.ctl->rq_head, &head, sizeof(head), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(&kp.ctl->rq_tail, &tail, sizeof(tail), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(&kp.ctl->remaining, &remaining, sizeof(remaining), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(kp.solves, sst.data(), sizeof(SolveState) * in.nprob, hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(kp.ring, ring.data(), sizeof(unsigned long long) * in.nring, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));  // the host arrays above are read before they go
+        if (ev.l0) HIPCHK(hipEventRecord(ev.l0, st));
+        kern<<<grid, 64 * W, lds, st>>>(kp);
+        HIPCHK(hipGetLastError());
+    } else if (o.launch_mode == FMM_LAUNCH_PERSISTENT) {
         auto kern = k_persistent<R, B, W>;
         HIPCHK(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * W, lds));
@@ -390,7 +475,8 @@ int launch_solve(KParams<R> &kp, const LaunchIn &in, const Device &dev, hipStrea
         void *args[] = {&kp};
         HIPCHK(hipLaunchCooperativeKernel((const void *)kern, dim3(grid), dim3(64 * W), args, lds, st));
     } else {
-        if (kp.stride_mode) return fail(FMM_ENOTSUP, "learned stride needs the persistent launch");
+        if (kp.stride_mode) return fail(FMM_ENOTSUP, "learned or scheduled strides need the persistent launch");
+        if (resume) return fail(FMM_ENOTSUP, "a resumed solve needs the persistent launch");
         auto km = k_march<R, B, W>;
         auto kx = k_exchange<R, B, W>;
         HIPCHK(hipFuncSetAttribute((const void *)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -437,9 +523,29 @@ int launch_solve(KParams<R> &kp, const LaunchIn &in, const Device &dev, hipStrea
     return 0;
 }
 
-// A solve on the library's cached arena (allocated and grown on demand).
+constexpr int32_t kSchedReserve = 1 << 16;  // bounds a resumed solve may be given
+
+// Identity of a launch's problem: what a resumed solve must share with the stopped one.
+std::string launch_signature(const std::vector<Prob> &probs, int B, int W, size_t rsize)
+{
+    std::string sig = "B" + std::to_string(B) + "W" + std::to_string(W) + "R" + std::to_string(rsize);
+    for (const Prob &pb : probs) {
+        sig += ":" + std::to_string(pb.d.nx) + "x" + std::to_string(pb.d.ny) + "x" + std::to_string(pb.d.nz);
+        for (const fmm_source &q : pb.src) {
+            char b[96];
+            std::snprintf(b, sizeof(b), "/%lld,%lld,%lld,%.17g", (long long)q.i, (long long)q.j,
+                          (long long)q.k, q.psi0);
+            sig += b;
+        }
+    }
+    return sig;
+}
+
+// A solve on the library's cached arena (allocated and grown on demand); resume_from > 0
+// continues the last solve on this device after that restart instead of starting one.
 template <typename R, int B, int W>
-int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, RunOut &out)
+int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, RunOut &out,
+              int64_t resume_from)
 {
     Device dev;
     if (int rc = device_info(dev)) return rc;
@@ -456,8 +562,38 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     std::vector<SrcEntry> ents;
     std::vector<int32_t> first;
     build_sources(probs, B, ents, first);
-    const WsLayout Lw = ws_layout<R, B>(nblk, nprob, ents.size());
-    if (int rc = ensure(ws.arena, Lw.total, "workspace")) return rc;
+    // per-problem restarts: the token ring holds every token that can be out at once
+    uint32_t nring = 0;
+    if (o.per_problem_restarts) {
+        if (resume_from > 0) return fail(FMM_ENOTSUP, "a batch with per-problem restarts cannot be resumed");
+        for (const ProbDesc &d : descs)
+            if (d.nblk >= (1 << 20) - (1 << 17))
+                return fail(FMM_EINVAL, "per-problem restarts: a problem has too many blocks");
+        // at most 32 one-wave work-groups fit on a compute unit, so the grid is below 32 * cus
+        const uint64_t need = (uint64_t)nprob * (uint64_t)batch_tokens((int64_t)32 * dev.cus, nprob);
+        if (need > (1u << 30)) return fail(FMM_EINVAL, "per-problem restarts: too many problems");
+        nring = 1;
+        while (nring < need) nring <<= 1;
+    }
+    // the layout is fixed by the problem; a schedule's bounds take the arena's last buffer
+    const WsLayout L0 = ws_layout<R, B>(nblk, nprob, ents.size(), 0);
+    const WsLayout Lw = ws_layout<R, B>(nblk, nprob, ents.size(),
+                                       o.stride_mode == FMM_STRIDE_SCHEDULE ? (size_t)o.nbounds : 0,
+                                       nring);
+    const std::string sig = launch_signature(probs, B, W, sizeof(R));
+    if (resume_from > 0) {
+        if (ws.last_sig != sig || !ws.arena.p)
+            return fail(FMM_EINVAL, "fmm_solve_resume: the last solve on this device was a different problem");
+        if (Lw.total > ws.arena.cap)
+            return fail(FMM_EINVAL, "fmm_solve_resume: the bound schedule does not fit the stopped solve's workspace");
+    } else {
+        // room for a later resume with a bound schedule of up to kSchedReserve bounds
+        if (int rc = ensure(ws.arena, std::max(Lw.total, L0.total + 8 * (size_t)kSchedReserve),
+                            "workspace"))
+            return rc;
+        ws.last_sig = sig;
+        ws.last_total = L0.total;
+    }
     if (!ws.e0) {
         HIPCHK(hipEventCreate(&ws.e0));
         HIPCHK(hipEventCreate(&ws.e1));
@@ -468,7 +604,8 @@ int run_solve(std::vector<Prob> &probs, const fmm_options &o, hipStream_t st, Ru
     char *base = (char *)ws.arena.p;
     ws_bind<R>(kp, base, Lw);
     LaunchIn in{descs.data(), nprob, nblk, ents.data(), (int32_t)ents.size(),
-                (SrcEntry *)(base + Lw.off[kWsSrc]), first.data(), (int32_t)first.size(), &o};
+                (SrcEntry *)(base + Lw.off[kWsSrc]), first.data(), (int32_t)first.size(), &o,
+                resume_from, nring};
     LaunchEvents ev{ws.e0, ws.e1, ws.l0, ws.l1};
     if (int rc = launch_solve<R, B, W>(kp, in, dev, st, ev, out.ctl, out.grid)) return rc;
     out.lastr.resize(nprob);
@@ -559,7 +696,8 @@ int run_solve_noalloc(const ProbDesc &d0, const fmm_source *src, int32_t nsrc, c
     int32_t first[kNoallocMaxEntries];
     int32_t nents = 0, nfirst = 0;
     if (int rc = build_sources_fixed(d, src, nsrc, B, ents, nents, first, nfirst)) return rc;
-    const WsLayout Lw = ws_layout<R, B>(nblk, 1, (size_t)nents);
+    const WsLayout Lw = ws_layout<R, B>(nblk, 1, (size_t)nents,
+                                       o.stride_mode == FMM_STRIDE_SCHEDULE ? (size_t)o.nbounds : 0);
     if (Lw.total > FMM_NOALLOC_SCRATCH_BYTES) {
         char msg[200];
         std::snprintf(msg, sizeof(msg),
@@ -598,11 +736,12 @@ NoallocFn pick_noalloc(int B, int W)
     FMM_CASE(16, 1)
     FMM_CASE(16, 2)
     FMM_CASE(16, 4)
+    FMM_CASE(32, 1)
 #undef FMM_CASE
     return nullptr;
 }
 
-using RunFn = int (*)(std::vector<Prob> &, const fmm_options &, hipStream_t, RunOut &);
+using RunFn = int (*)(std::vector<Prob> &, const fmm_options &, hipStream_t, RunOut &, int64_t);
 
 template <typename R>
 RunFn pick(int B, int W)
@@ -618,11 +757,13 @@ RunFn pick(int B, int W)
     FMM_CASE(16, 1)
     FMM_CASE(16, 2)
     FMM_CASE(16, 4)
+    FMM_CASE(32, 1)
 #undef FMM_CASE
     return nullptr;
 }
 
-int dispatch(int dtype, int B, const fmm_options &o, std::vector<Prob> &probs, hipStream_t st, RunOut &out)
+int dispatch(int dtype, int B, const fmm_options &o, std::vector<Prob> &probs, hipStream_t st, RunOut &out,
+             int64_t resume_from = 0)
 {
     const int W = o.waves_per_block <= 0 ? 1 : o.waves_per_block;
     if (W != 1 && W != 2 && W != 4) return fail(FMM_EINVAL, "waves_per_block must be 1, 2 or 4");
@@ -630,21 +771,36 @@ int dispatch(int dtype, int B, const fmm_options &o, std::vector<Prob> &probs, h
     if (dtype == FMM_F32) fn = pick<float>(B, W);
     else if (dtype == FMM_F64) fn = pick<double>(B, W);
     else return fail(FMM_EINVAL, "dtype must be FMM_F32 or FMM_F64");
-    if (!fn) return fail(FMM_ENOTSUP, "unsupported block / waves combination");
-    return fn(probs, o, st, out);
+    if (!fn)
+        return fail(FMM_ENOTSUP, B == 32 ? "32^3 blocks march with one wave per block"
+                                         : "unsupported block / waves combination");
+    return fn(probs, o, st, out, resume_from);
 }
 
 int check_options(const fmm_options &o)
 {
     if (!(o.width > 0)) return fail(FMM_EINVAL, "width must be > 0");
-    if (o.stride_mode != FMM_STRIDE_FIXED && o.stride_mode != FMM_STRIDE_LEARNED)
+    if (o.stride_mode != FMM_STRIDE_FIXED && o.stride_mode != FMM_STRIDE_LEARNED &&
+        o.stride_mode != FMM_STRIDE_SCHEDULE)
         return fail(FMM_EINVAL, "unknown stride_mode");
+    if (o.stride_mode == FMM_STRIDE_SCHEDULE) {
+        if (!o.bounds || o.nbounds < 1 || o.nbounds > (1 << 24))
+            return fail(FMM_EINVAL, "a bound schedule needs 1 to 2^24 bounds");
+        for (int32_t k = 0; k < o.nbounds; ++k)
+            if (!(o.bounds[k] > 0) || !std::isfinite(o.bounds[k]) || (k > 0 && o.bounds[k] < o.bounds[k - 1]))
+                return fail(FMM_EINVAL, "bound schedule: values must be finite, > 0 and non-decreasing");
+    }
     if (o.launch_mode != FMM_LAUNCH_PERSISTENT && o.launch_mode != FMM_LAUNCH_HOST)
         return fail(FMM_EINVAL, "unknown launch_mode");
     if (o.trace_dev && o.trace_cap < 0) return fail(FMM_EINVAL, "trace_cap must be >= 0");
     if (o.max_restarts < 0) return fail(FMM_EINVAL, "max_restarts must be >= 0");
     if (o.band_lds_cap < 0 || o.band_lds_cap % 512)
         return fail(FMM_EINVAL, "band_lds_cap must be a non-negative multiple of 512");
+    if (o.per_problem_restarts != 0 && o.per_problem_restarts != 1)
+        return fail(FMM_EINVAL, "per_problem_restarts must be 0 or 1");
+    if (o.per_problem_restarts &&
+        (o.stride_mode != FMM_STRIDE_FIXED || o.launch_mode != FMM_LAUNCH_PERSISTENT))
+        return fail(FMM_ENOTSUP, "per-problem restarts need a fixed stride and the persistent launch");
     return 0;
 }
 
@@ -822,8 +978,8 @@ int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const
         if (int rc = check_options(o)) return rc;
         if (int rc = validate_problem(nx, ny, nz, h, F_dev, psi_dev, src, nsrc, block, stride, "fmm_solve"))
             return rc;
-        if (o.stride_mode == FMM_STRIDE_LEARNED && !std::isfinite(stride))
-            return fail(FMM_EINVAL, "learned stride needs a finite base stride");
+        if (o.stride_mode != FMM_STRIDE_FIXED && !std::isfinite(stride))
+            return fail(FMM_EINVAL, "learned or scheduled strides need a finite base stride");
         std::vector<Prob> probs(1);
         ProbDesc &d = probs[0].d;
         std::memset(&d, 0, sizeof(d));
@@ -849,6 +1005,81 @@ int fmm_solve(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const
     }
 }
 
+int fmm_solve_resume(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
+                     const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
+                     void *hip_stream, const fmm_options *opt, int64_t from_restart, fmm_stats *stats)
+{
+    try {
+        fmm_options o;
+        fmm_options_default(&o);
+        if (opt) o = *opt;
+        if (int rc = check_options(o)) return rc;
+        if (int rc = validate_problem(nx, ny, nz, h, F_dev, psi_dev, src, nsrc, block, stride, "resume"))
+            return rc;
+        if (from_restart < 1) return fail(FMM_EINVAL, "fmm_solve_resume: from_restart must be >= 1");
+        if (o.stride_mode == FMM_STRIDE_LEARNED)
+            return fail(FMM_ENOTSUP, "fmm_solve_resume: fixed strides and bound schedules only");
+        if (o.stride_mode == FMM_STRIDE_SCHEDULE && o.nbounds > kSchedReserve)
+            return fail(FMM_EINVAL, "fmm_solve_resume: at most 65536 bounds");
+        if (o.launch_mode != FMM_LAUNCH_PERSISTENT)
+            return fail(FMM_ENOTSUP, "fmm_solve_resume: persistent launch only");
+        if (o.stride_mode == FMM_STRIDE_SCHEDULE && !std::isfinite(stride))
+            return fail(FMM_EINVAL, "fmm_solve_resume: a bound schedule needs a finite stride");
+        std::vector<Prob> probs(1);
+        ProbDesc &d = probs[0].d;
+        std::memset(&d, 0, sizeof(d));
+        d.F = F_dev;
+        d.psi = psi_dev;
+        d.nx = (int32_t)nx;
+        d.ny = (int32_t)ny;
+        d.nz = (int32_t)nz;
+        d.h = h;
+        d.stride = stride;
+        d.width = o.width;
+        probs[0].src.assign(src, src + nsrc);
+        RunOut out{};
+        int rc = dispatch(dtype, block, o, probs, (hipStream_t)hip_stream, out, from_restart);
+        if (stats && (rc == 0 || rc == FMM_ENOCONV))
+            fill_stats(stats, out, block, o.waves_per_block <= 0 ? 1 : o.waves_per_block,
+                       out.ctl.restarts, (int64_t)out.ctl.pops);
+        return rc;
+    } catch (const std::exception &e) {
+        return fail(FMM_EHIP, std::string("fmm_solve_resume: ") + e.what());
+    } catch (...) {
+        return fail(FMM_EHIP, "fmm_solve_resume: unknown exception");
+    }
+}
+
+int fmm_workspace_save(void *dst_dev, size_t cap_bytes, size_t *bytes_out, void *hip_stream)
+{
+    Device dev;
+    if (int rc = device_info(dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace &ws = g_ws[dev.id];
+    if (bytes_out) *bytes_out = ws.last_total;
+    if (!ws.arena.p || ws.last_total == 0) return fail(FMM_EINVAL, "fmm_workspace_save: no solve on this device yet");
+    if (!dst_dev) return 0;  // size query
+    if (cap_bytes < ws.last_total) return fail(FMM_EINVAL, "fmm_workspace_save: destination too small");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIPCHK(hipMemcpyAsync(dst_dev, ws.arena.p, ws.last_total, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
+int fmm_workspace_restore(const void *src_dev, size_t bytes, void *hip_stream)
+{
+    Device dev;
+    if (int rc = device_info(dev)) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace &ws = g_ws[dev.id];
+    if (!src_dev || !ws.arena.p || ws.last_total == 0 || bytes != ws.last_total)
+        return fail(FMM_EINVAL, "fmm_workspace_restore: not a saved state of the last solve on this device");
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIPCHK(hipMemcpyAsync(ws.arena.p, src_dev, bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return 0;
+}
+
 int fmm_solve_noalloc(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtype, const void *F_dev,
                       const fmm_source *src, int32_t nsrc, int32_t block, double stride, void *psi_dev,
                       void *hip_stream, const fmm_options *opt, fmm_stats *stats)
@@ -860,8 +1091,8 @@ int fmm_solve_noalloc(int64_t nx, int64_t ny, int64_t nz, double h, int32_t dtyp
         if (int rc = check_options(o)) return rc;
         if (int rc = validate_problem(nx, ny, nz, h, F_dev, psi_dev, src, nsrc, block, stride, "noalloc"))
             return rc;
-        if (o.stride_mode == FMM_STRIDE_LEARNED && !std::isfinite(stride))
-            return fail(FMM_EINVAL, "fmm_solve_noalloc: learned stride needs a finite base stride");
+        if (o.stride_mode != FMM_STRIDE_FIXED && !std::isfinite(stride))
+            return fail(FMM_EINVAL, "fmm_solve_noalloc: learned or scheduled strides need a finite base stride");
         if (nsrc > kNoallocMaxSources)
             return fail(FMM_EINVAL, "fmm_solve_noalloc: at most 256 sources");
         const int W = o.waves_per_block <= 0 ? 1 : o.waves_per_block;
@@ -959,7 +1190,7 @@ int fmm_autotune(int32_t nsamples, const fmm_problem *samples, int32_t dtype, co
             return 0;
         }
         best = fmm_tuning{0, 0, INFINITY};
-        const int blocks[2] = {8, 16};
+        const int blocks[3] = {8, 16, 32};
         const int waves[3] = {1, 2, 4};
         for (int B : blocks) {
             bool divides = true;
@@ -967,6 +1198,7 @@ int fmm_autotune(int32_t nsamples, const fmm_problem *samples, int32_t dtype, co
                 if (samples[q].nx % B || samples[q].ny % B || samples[q].nz % B) divides = false;
             if (!divides) continue;
             for (int W : waves) {
+                if (B == 32 && W != 1) continue;  // 32^3 blocks march with one wave
                 fmm_options o;
                 fmm_options_default(&o);
                 o.waves_per_block = W;
@@ -1022,6 +1254,30 @@ int fmm_selftest_band_argmin(int dtype, int32_t block, const void *psi_dev, cons
     } catch (const std::exception &ex) {
         return fail(FMM_EHIP, std::string("fmm_selftest_band_argmin: ") + ex.what());
     }
+}
+
+int fmm_release(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    int cur = 0;
+    // no device call at all when no solve ever ran (nothing to free on any device)
+    const bool have_cur = !g_ws.empty() && hipGetDevice(&cur) == hipSuccess;
+    for (auto &kv : g_ws) {
+        if (hipSetDevice(kv.first) != hipSuccess) continue;
+        Workspace &ws = kv.second;
+        if (ws.arena.p) (void)hipFree(ws.arena.p);
+        hipEvent_t *evs[4] = {&ws.e0, &ws.e1, &ws.l0, &ws.l1};
+        for (hipEvent_t *e : evs) {
+            if (*e) (void)hipEventDestroy(*e);
+            *e = nullptr;
+        }
+    }
+    g_ws.clear();
+    if (have_cur) (void)hipSetDevice(cur);
+    fmm_internal_mlp_release();
+    g_tune_cache.clear();
+    for (int d = 0; d < kMaxDevices; ++d) g_scratch_ptr[d] = nullptr;
+    return 0;
 }
 
 const char *fmm_strerror(int code)

@@ -112,6 +112,27 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
     __syncthreads();
 }
 
+// Where a block's list entries go: the next march list (4 work bins of `stride` entries
+// from `next`, counted in bins[] and *nlist) and the exchange list (xl, counted in *xn),
+// each holding at most `cap` entries.  Either the whole launch's lists (restarts shared by
+// every problem) or one problem's segment of them (restarts of its own).
+struct ListSink {
+    int32_t *next;
+    int *bins;
+    int *nlist;
+    int32_t *xl;
+    int *xn;
+    int64_t stride, cap;
+};
+
+// The lists of the whole launch in restart r (list parity c = r & 1).
+template <typename R>
+__device__ __forceinline__ ListSink launch_sink(const KParams<R> &kp, int c)
+{
+    return ListSink{c ? kp.list0 : kp.list1, kp.ctl->bin_n[c ^ 1], &kp.ctl->n_list[c ^ 1],
+                    kp.xlist, &kp.ctl->x_n[c], kp.nblk, kp.nblk};
+}
+
 // ---------------------------------------------------------------- Alg. 4 on one block
 // March_Narrow_Band(ib): load the block's tile, band and tags into LDS, accept
 // band points in increasing (psi, index) order while psi <= bound, relaxing the
@@ -127,18 +148,18 @@ __device__ void grid_barrier(Ctl *ctl, unsigned G, int64_t timeout_ticks)
 // that covers the h^2/F^2 load from device memory, issued first).
 template <typename R, int B, int W>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
-                            int c, char *smem, unsigned long long &pops_acc, bool &a_out,
+                            const ListSink &sink, char *smem, unsigned long long &pops_acc, bool &a_out,
                             int &n_out, int &pops_out FMM_CYC_PARAM)
 {
     using L = Lds<R, B, W>;
     using Gm = Geo<B>;
     constexpr int P = Gm::P, T = Gm::T, NT = 64 * W, BAND = Gm::BAND, TAGB = Gm::TAGB;
+    constexpr bool TL = Gm::TILE_LDS;  // tile staged in LDS (else marched in device memory)
+    static_assert(TL || W == 1, "a tile in device memory is marched by one wave");
     // band slots [0, cap) live in LDS, [cap, n) in the block's band array in memory
     const int cap = kp.band_cap > 0 && kp.band_cap < Gm::BANDC ? kp.band_cap : Gm::BANDC;
     FMM_LDS char *lds = (FMM_LDS char *)smem;
-    FMM_LDS R *s_psi = reinterpret_cast<FMM_LDS R *>(lds + L::psi_off);
     FMM_LDS uint16_t *s_band = reinterpret_cast<FMM_LDS uint16_t *>(lds + L::band_off);
-    FMM_LDS uint8_t *s_tag = reinterpret_cast<FMM_LDS uint8_t *>(lds + L::tag_off);
     __shared__ int s_bc[1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const R inf = (R)INFINITY;
@@ -147,17 +168,30 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     uint8_t *g_tag = kp.tag_t + ib * (int64_t)TAGB;
     uint16_t *g_band = kp.band_t + ib * (int64_t)BAND;
     const R *g_rhs = kp.rhs_t + ib * (int64_t)T;
+    typename TilePtr<R, TL>::type s_psi;
+    typename TilePtr<uint8_t, TL>::type s_tag;
+    if constexpr (TL) {
+        s_psi = reinterpret_cast<FMM_LDS R *>(lds + L::psi_off);
+        s_tag = reinterpret_cast<FMM_LDS uint8_t *>(lds + L::tag_off);
+    } else {
+        s_psi = g_psi;
+        s_tag = g_tag;
+    }
 
     FMM_CYC_START();
     int n = kp.band_n[ib];
-    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_psi),
-                                               reinterpret_cast<const v4u *>(g_psi), tid);
-    copy_vec16<NT, TAGB / 16>(reinterpret_cast<FMM_LDS v4u *>(s_tag),
-                              reinterpret_cast<const v4u *>(g_tag), tid);
+    if constexpr (TL) {
+        copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_psi),
+                                                   reinterpret_cast<const v4u *>(g_psi), tid);
+        copy_vec16<NT, TAGB / 16>(reinterpret_cast<FMM_LDS v4u *>(s_tag),
+                                  reinterpret_cast<const v4u *>(g_tag), tid);
+    }
     copy_band<NT>(reinterpret_cast<FMM_LDS v4u *>(s_band), reinterpret_cast<const v4u *>(g_band),
                   n < cap ? n : cap, tid);
     FMM_LDS R *s_rhs = reinterpret_cast<FMM_LDS R *>(lds + L::rhs_off);
-    if constexpr (Gm::RHS_LDS) {
+    if constexpr (!TL) {
+        // the tile is marched where it is; h^2/F^2 is read from memory as needed
+    } else if constexpr (Gm::RHS_LDS) {
         copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<FMM_LDS v4u *>(s_rhs),
                                                    reinterpret_cast<const v4u *>(g_rhs), tid);
     } else {
@@ -176,10 +210,15 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     FMM_CYC_FULL(6);
     FMM_CYC_COUNT(13, 1);
 
-    // per-lane neighbour direction of Update_Neighbors: lanes 0-5 = -x, +x, -y, +y, -z, +z
-    const int dI = (lane == 1) - (lane == 0), dJ = (lane == 3) - (lane == 2),
-              dK = (lane == 5) - (lane == 4);
+    // Update_Neighbors by quads of wave 0: quad g (lanes 4g .. 4g+3, g < 6) takes face
+    // neighbour g of the accepted point (-x, +x, -y, +y, -z, +z); its lanes kk = 0, 1, 2
+    // solve the quadratic of Alg. 3 with kk + 1 candidates at once, and lane 4g takes the
+    // root the sequential rule of Alg. 3 arrives at.  Lane 24 retags the accepted point,
+    // lane 25 moves the band's last slot (Remove_Min).
+    const int g = lane >> 2, kk = lane & 3;
+    const int dI = (g == 1) - (g == 0), dJ = (g == 3) - (g == 2), dK = (g == 5) - (g == 4);
     const int dOff = dI + P * (dJ + P * dK);
+    uint32_t mine = 0;  // faces of Upsilon, recorded as points are lowered (tile in memory)
     constexpr int kMid = (B / 2) * (1 + P + P * P);  // an interior point of the tile
     bool active = true;
     R exit_min = inf;
@@ -200,13 +239,15 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             break;
         }
         const int p = mp.idx;
+        FMM_CYC_COUNT(14, n <= 64 ? 1 : 0);  // band sizes at the pick (profiling build)
+        FMM_CYC_COUNT(15, n <= 256 ? 1 : 0);
         if (++npops > pop_cap) {
             raise_error(kp.ctl, kErrPopCap);
             exit_min = mp.v;
             break;
         }
         n -= 1;  // Remove_Min: the last slot moves into the hole (lane 7 below)
-        // Update_Neighbors(p): lanes 0-5 take the six face neighbours (interior only)
+        // Update_Neighbors(p): quads 0-5 take the six face neighbours (interior only)
         if (wid == 0) {
             // h^2/F^2 of the lane's neighbour from device memory, issued before anything
             // else of the step (the index is clamped to the tile; unused when the
@@ -219,7 +260,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             const uint32_t up = (uint32_t)p;
             const int pi = (int)(up % P), pj = (int)((up / P) % P), pk = (int)(up / (P * P));
             const int qi = pi + dI, qj = pj + dJ, qk = pk + dK;
-            const bool inb = lane < 6 && (unsigned)(qi - 1) < (unsigned)B &&
+            const bool inb = lane < 24 && kk < 3 && (unsigned)(qi - 1) < (unsigned)B &&
                              (unsigned)(qj - 1) < (unsigned)B && (unsigned)(qk - 1) < (unsigned)B;
             const int q = inb ? p + dOff : p;
             R rhs = (R)0;
@@ -227,11 +268,11 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 if constexpr (Gm::RHS_LDS) rhs = s_rhs[q];
                 else rhs = rhs_mem;
             }
-            const uint8_t tq = s_tag[q];  // lane 6 reads the accepted point's own tag
+            const uint8_t tq = s_tag[q];  // lane 24 reads the accepted point's own tag
             const R psq = s_psi[q];
             // With h^2/F^2 in LDS (small blocks) the stencil of q is read in the same
             // round trip: its points are not written in this step (the six neighbours are
-            // pairwise not face-adjacent), except p's tag, which lane 6 turns KNOWN below;
+            // pairwise not face-adjacent), except p's tag, which lane 24 turns KNOWN below;
             // p is taken as known instead.  Lanes without a neighbour read around an
             // interior point of the tile (unused).  With h^2/F^2 in device memory the
             // stencil is read after the check below, while that load is in flight.
@@ -248,45 +289,47 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     thi[ax] = s_tag[qs + off];
                 }
             }
-            // Remove_Min: lane 7 moves the band's last slot into the hole.  The branch on
+            // Remove_Min: lane 25 moves the band's last slot into the hole.  The branch on
             // the wave-uniform n < cap keeps the usual all-LDS case free of any wait on
             // device memory (the h^2/F^2 load above stays in flight until the solve).
             if (n < cap) {
                 const uint16_t last = (uint16_t)__builtin_amdgcn_readfirstlane(s_band[n]);
-                if (lane == 7) s_band[mp.slot] = last;  // mp.slot <= n < cap
+                if (lane == 25) s_band[mp.slot] = last;  // mp.slot <= n < cap
             } else {
                 // every lane reads the same slot; taking it as a wave-uniform value also
                 // completes the load inside this branch
                 const uint16_t last =
                     (uint16_t)__builtin_amdgcn_readfirstlane(__builtin_nontemporal_load(g_band + n));
-                if (lane == 7) {
+                if (lane == 25) {
                     if (mp.slot < cap) s_band[mp.slot] = last;
                     else __builtin_nontemporal_store(last, g_band + mp.slot);
                 }
             }
-            if (lane == 6)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
+            if (lane == 24)  // KNOWN_NEW unless KNOWN_FIX; leaves the band
                 s_tag[p] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
             FMM_CYC(3);
             FMM_CYC_COUNT(12, 1);
-            bool ins = false;
-            if (inb && (tq & kStatus) != kKnownFix && psq > mp.v) {
+            // the same in the three lanes of a quad (same neighbour, same reads)
+            const bool solve = inb && (tq & kStatus) != kKnownFix && psq > mp.v;
+            R t = inf, v1 = inf, v2 = inf;
+            if (solve) {
                 FMM_CYC_LSTART();
                 R c[3];
 #pragma unroll
                 for (int ax = 0; ax < 3; ++ax) {
                     bool klo, khi;
                     if constexpr (Gm::RHS_LDS) {
-                        // p is q's low neighbour for the + directions (odd lanes) and its
-                        // high neighbour for the - directions, on the lane's own axis
-                        const bool own = ax == (lane >> 1);
-                        klo = is_known(tlo[ax]) || (own && (lane & 1));
-                        khi = is_known(thi[ax]) || (own && !(lane & 1));
+                        // p is q's low neighbour for the + directions (odd quads) and its
+                        // high neighbour for the - directions, on the quad's own axis
+                        const bool own = ax == (g >> 1);
+                        klo = is_known(tlo[ax]) || (own && (g & 1));
+                        khi = is_known(thi[ax]) || (own && !(g & 1));
                     } else {
                         const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
                         lo[ax] = s_psi[q - off];
                         hi[ax] = s_psi[q + off];
-                        // p itself reads as known: lane 6 wrote its tag above, and one
-                        // wave's LDS accesses complete in program order
+                        // p itself reads as known: lane 24 wrote its tag above, and one
+                        // wave's accesses to one address complete in program order
                         klo = is_known(s_tag[q - off]);
                         khi = is_known(s_tag[q + off]);
                     }
@@ -294,14 +337,29 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 }
                 FMM_CYC_L(8);
                 FMM_CYC_LFULL(9);
-                const R t = quad_root<R>(c[0], c[1], c[2], rhs);
-                if (t < psq) {
-                    s_psi[q] = t;
-                    s_tag[q] = kBand | kInBand;
-                    ins = !(tq & kInBand);
-                }
+                t = quad_root_k<R>(c[0], c[1], c[2], rhs, kk, v1, v2);
                 FMM_CYC_L(10);
                 FMM_CYC_COUNT(11, 1);
+            }
+            // lane 4g: the root with one candidate, then while it exceeds the next candidate
+            // the root with one more (Alg. 3), from the quad's other lanes
+            const R t2 = quad_bcast<1>(t), t3 = quad_bcast<2>(t);
+            bool ins = false;
+            if (solve && kk == 0) {
+                R tf = t;
+                if (v1 < inf && tf > v1) {
+                    tf = t2;
+                    if (v2 < inf && tf > v2) tf = t3;
+                }
+                if (tf < psq) {
+                    s_psi[q] = tf;
+                    s_tag[q] = kBand | kInBand;
+                    ins = !(tq & kInBand);
+                    if constexpr (!TL) {  // q on a boundary layer: its faces join Upsilon
+                        mine |= (qi == 1 ? 1u : 0u) | (qi == B ? 2u : 0u) | (qj == 1 ? 4u : 0u) |
+                                (qj == B ? 8u : 0u) | (qk == 1 ? 16u : 0u) | (qk == B ? 32u : 0u);
+                    }
+                }
             }
             FMM_CYC(4);
             const uint64_t bal = ballot(ins);
@@ -311,9 +369,9 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 else __builtin_nontemporal_store((uint16_t)q, g_band + at);
             }
             n += (int)__popcll(bal);
-            if (n + 8 > cap) {
-                // the band reaches its memory part: make this wave's stores to it
-                // visible to its own later loads
+            if (!TL || n + 8 > cap) {
+                // the band reaches its memory part, or the tile is in memory: make this
+                // wave's stores there visible to its own later loads
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
@@ -337,14 +395,15 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     // smaller value (every update of Update_Neighbors is a strict decrease, and nothing else
     // writes psi in the march); the block's tile in memory still holds the values the march
     // started from
-    constexpr int NF = 6 * B * B, FPER = (NF + NT - 1) / NT;
-    uint32_t mine = 0;
+    if constexpr (TL) {
+        constexpr int NF = 6 * B * B, FPER = (NF + NT - 1) / NT;
 #pragma unroll 4
-    for (int k = 0; k < FPER; ++k) {
-        const int e = tid + k * NT;
-        if (e < NF) {
-            const int t = face_point<B>(e);
-            if (s_psi[t] < g_psi[t]) mine |= 1u << (e / (B * B));
+        for (int k = 0; k < FPER; ++k) {
+            const int e = tid + k * NT;
+            if (e < NF) {
+                const int t = face_point<B>(e);
+                if (s_psi[t] < g_psi[t]) mine |= 1u << (e / (B * B));
+            }
         }
     }
     uint32_t dirty = 0;
@@ -359,10 +418,12 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         dirty = s_dirty[0];
     }
     // LDS -> tile
-    copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<v4u *>(g_psi),
-                                               reinterpret_cast<const FMM_LDS v4u *>(s_psi), tid);
-    copy_vec16<NT, TAGB / 16>(reinterpret_cast<v4u *>(g_tag),
-                              reinterpret_cast<const FMM_LDS v4u *>(s_tag), tid);
+    if constexpr (TL) {
+        copy_vec16<NT, (int)(sizeof(R) * T / 16)>(reinterpret_cast<v4u *>(g_psi),
+                                                   reinterpret_cast<const FMM_LDS v4u *>(s_psi), tid);
+        copy_vec16<NT, TAGB / 16>(reinterpret_cast<v4u *>(g_tag),
+                                  reinterpret_cast<const FMM_LDS v4u *>(s_tag), tid);
+    }
     copy_band<NT>(reinterpret_cast<v4u *>(g_band), reinterpret_cast<const FMM_LDS v4u *>(s_band),
                   n < cap ? n : cap, tid);
     if (tid == 0) {
@@ -384,8 +445,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             const int64_t nb = pd.blk0 + bx + (int64_t)pd.mx * (by + (int64_t)pd.my * bz);
             // the first flag raised on nb in this restart puts nb on the exchange list
             if (atomicOr(&kp.Cm[nb], 1u << (f ^ 1)) == 0u) {
-                const int pos = atomicAdd(&kp.ctl->x_n[c], 1);
-                if (pos < kp.nblk) kp.xlist[pos] = (int32_t)nb;
+                const int pos = atomicAdd(sink.xn, 1);
+                if (pos < sink.cap) sink.xl[pos] = (int32_t)nb;
                 else raise_error(kp.ctl, kErrList);  // cannot happen: one entry per block
             }
         }
@@ -509,16 +570,15 @@ __device__ __forceinline__ int band_bin(int nb)
 // one of 4 bins by its expected work est (longest first), and add it to the restart
 // features.  One thread per block.
 template <typename R>
-__device__ void append_next(const KParams<R> &kp, int c, int64_t r, int64_t ib, int est, int nb,
-                            unsigned long long *lfeat)
+__device__ void append_next(const KParams<R> &kp, const ListSink &sink, int64_t r, int64_t ib, int est,
+                            int nb, unsigned long long *lfeat)
 {
     Ctl *ctl = kp.ctl;
-    int32_t *next = c ? kp.list0 : kp.list1;
     const int k = est >= 768 ? 0 : (est >= 256 ? 1 : (est >= 64 ? 2 : 3));
-    const int pos = atomicAdd(&ctl->bin_n[c ^ 1][k], 1);
-    if (pos < kp.nblk) next[(int64_t)k * kp.nblk + pos] = (int32_t)ib;
+    const int pos = atomicAdd(&sink.bins[k], 1);
+    if (pos < sink.cap) sink.next[(int64_t)k * sink.stride + pos] = (int32_t)ib;
     else raise_error(ctl, kErrList);  // cannot happen: one entry per block
-    atomicAdd(&ctl->n_list[c ^ 1], 1);
+    atomicAdd(sink.nlist, 1);
     if (kp.want_features) {  // the work-group's sums, added to ctl->feat by flush_features
         lfeat[band_bin(nb)] += 1ull;
         lfeat[8] += (unsigned long long)((double)kp.fmean[ib] * kFixScale + 0.5);
@@ -620,7 +680,7 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
                 if ((double)bm > pd.width) kp.A[ib] = 0;
                 else {
                     const int nb = kp.band_n[ib];
-                    append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nb), nb, s_feat);
+                    append_next<R>(kp, launch_sink(kp, c), r, ib, max(kp.lastpops[ib], nb), nb, s_feat);
                 }
             }
             continue;
@@ -634,8 +694,9 @@ __device__ void march_phase(const KParams<R> &kp, int64_t r, double lbound, char
         }
         bool a;
         int nb, np;
-        march_block<R, B, W>(kp, ib, pd, bound, c, smem, pops, a, nb, np FMM_CYC_ARG);
-        if (tid == 0 && a) append_next<R>(kp, c, r, ib, max(np, nb), nb, s_feat);
+        const ListSink sink = launch_sink(kp, c);
+        march_block<R, B, W>(kp, ib, pd, bound, sink, smem, pops, a, nb, np FMM_CYC_ARG);
+        if (tid == 0 && a) append_next<R>(kp, sink, r, ib, max(np, nb), nb, s_feat);
     }
     if (tid == 0 && kp.want_features) flush_features(ctl, c ^ 1, s_feat);
     tot.pops += pops;
@@ -686,7 +747,7 @@ __device__ void exchange_phase(const KParams<R> &kp, int64_t r, char *smem, int 
         ++xcalls;
         if (tid == 0) {
             if (an && !a0) {
-                append_next<R>(kp, c, r, ib, max(kp.lastpops[ib], nn), nn, s_feat);
+                append_next<R>(kp, launch_sink(kp, c), r, ib, max(kp.lastpops[ib], nn), nn, s_feat);
             } else if (a0 && kp.want_features && band_bin(nn) != band_bin(n0)) {
                 s_feat[band_bin(n0)] += ~0ull;  // -1 (modulo 2^64, like the totals)
                 s_feat[band_bin(nn)] += 1ull;
@@ -753,12 +814,24 @@ __global__ void __launch_bounds__(64 * W)
     if (read_abort(ctl)) return;
     const ProbDesc &p0 = kp.prob[0];
     double prev_bound = 0.0, lstride = p0.stride, lbound = 0.0;
+    if (kp.r0 > 0) {  // resumed after restart r0 (fixed stride or a bound schedule)
+        prev_bound = kp.stride_mode == 2
+                         ? (kp.r0 <= kp.nsched ? kp.sched[kp.r0 - 1]
+                                               : kp.sched[kp.nsched - 1] + (double)(kp.r0 - kp.nsched) * p0.stride)
+                         : fixed_bound(kp.r0, p0.stride, p0.width);
+        if (prev_bound > p0.width) prev_bound = p0.width;
+    }
     Totals tot;
     FMM_CYC_DECL;
-    for (int64_t r = 1;; ++r) {
+    for (int64_t r = kp.r0 + 1;; ++r) {
         const int c = (int)(r & 1);
-        if (kp.stride_mode) {
+        if (kp.stride_mode == 1) {
             lbound = prev_bound + lstride;
+            if (lbound > p0.width) lbound = p0.width;
+        } else if (kp.stride_mode == 2) {
+            // a given bound sequence, then the last bound plus the stride per restart
+            lbound = r <= kp.nsched ? kp.sched[r - 1]
+                                    : kp.sched[kp.nsched - 1] + (double)(r - kp.nsched) * p0.stride;
             if (lbound > p0.width) lbound = p0.width;
         }
         int64_t t0 = 0;
@@ -824,7 +897,7 @@ __global__ void __launch_bounds__(64 * W)
             }
             break;
         }
-        if (kp.stride_mode) {
+        if (kp.stride_mode == 1) {
             float m = 1.0f;
             if (kp.mlp) {
                 m = mlp_multiplier(kp.mlp, feat);
@@ -840,6 +913,284 @@ __global__ void __launch_bounds__(64 * W)
 #ifdef FMM_CYCLES
     cyc.flush();
 #endif
+}
+
+// ---------------------------------------------------------------- batches: restarts per problem
+// A batch whose problems restart on their own: no barrier is shared between problems.
+// Each problem runs Alg. 6 as a sequence of phases (the marching step of restart r, then
+// its exchanging step), each a list of work items (blocks).  A work-group takes a token
+// of some problem from the ready queue and claims that problem's items one at a time
+// (one atomic on the problem's phase word); the work-group that finishes a phase's last
+// item starts the problem's next phase and puts its tokens in the queue.  Within a problem
+// the phases follow each other as in the launch-wide loop, with the same lists, so every
+// problem's psi and counts are those of its own solve.
+
+// The ready queue: a bounded ring of 64-bit slots (sequence << 32 | problem) in which every
+// producer and consumer takes a position by compare-and-swap and waits on the slot's
+// sequence (the classic bounded multi-producer multi-consumer queue).  A problem keeps at
+// most kp.tokens tokens in it (SolveState::queued) and the capacity is at least that many
+// per problem, so a push never finds it full.
+// Every wait in the queue ends: each pass that does not take a slot counts a poll, and every
+// 64 polls the work-group reads the abort flag and the watchdog.  The watchdog measures time
+// in which no token was put in anywhere in the launch; tokens are only put in when a phase
+// starts (at most kp.tokens per start), so once the phases stop the waits run out.
+template <typename R>
+__device__ __forceinline__ bool ring_wait_over(const KParams<R> &kp, int &polls, unsigned long long &seen,
+                                               int64_t &t0)
+{
+    if ((++polls & 63) != 0) return false;
+    Ctl *ctl = kp.ctl;
+    if (read_abort(ctl)) return true;
+    const unsigned long long tl = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (tl != seen) {  // tokens are still being put in: progress
+        seen = tl;
+        t0 = wall_ticks();
+        return false;
+    }
+    if (wall_ticks() - t0 > kp.timeout_ticks) {
+        raise_error(ctl, kErrTimeout);
+        return true;
+    }
+    return false;
+}
+
+template <typename R>
+__device__ void ring_push(const KParams<R> &kp, int q)
+{
+    Ctl *ctl = kp.ctl;
+    unsigned long long pos = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long seen = pos;
+    int64_t t0 = wall_ticks();
+    int polls = 0;
+    for (;;) {
+        unsigned long long *slot = kp.ring + (pos & kp.ring_mask);
+        const unsigned long long v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int dif = (int)((uint32_t)(v >> 32) - (uint32_t)pos);
+        if (dif == 0) {
+            if (__hip_atomic_compare_exchange_strong(&ctl->rq_tail, &pos, pos + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(slot, ((unsigned long long)(uint32_t)(pos + 1) << 32) | (uint32_t)q,
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            // pos now holds the current tail
+        } else {
+            if (dif < 0) __builtin_amdgcn_s_sleep(2);  // full: cannot happen with the capacity chosen
+            pos = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ring_wait_over<R>(kp, polls, seen, t0)) return;  // aborting: the token is not needed
+    }
+}
+
+// A token, or -1 when every problem has finished, the launch is aborting, or no token was
+// put in anywhere for the watchdog's time.
+template <typename R>
+__device__ int ring_pop(const KParams<R> &kp)
+{
+    Ctl *ctl = kp.ctl;
+    if (read_abort(ctl)) return -1;
+    unsigned long long pos = __hip_atomic_load(&ctl->rq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long seen = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int64_t t0 = wall_ticks();
+    int polls = 0;
+    for (;;) {
+        unsigned long long *slot = kp.ring + (pos & kp.ring_mask);
+        const unsigned long long v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int dif = (int)((uint32_t)(v >> 32) - (uint32_t)(pos + 1));
+        if (dif == 0) {
+            if (__hip_atomic_compare_exchange_strong(&ctl->rq_head, &pos, pos + 1, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                __hip_atomic_store(slot, (unsigned long long)(uint32_t)(pos + kp.ring_mask + 1) << 32,
+                                   __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                const int q = (int)(uint32_t)v;
+                if (q >= kp.nprob) return q;  // the caller reports it
+                // acquire: a phase start that counted this token stored its phase word first
+                __hip_atomic_fetch_add(&kp.solves[q].queued, -1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                return q;
+            }
+            // pos now holds the current head
+        } else {
+            if (dif < 0) {  // empty
+                if (__hip_atomic_load(&ctl->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0)
+                    return -1;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            pos = __hip_atomic_load(&ctl->rq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ring_wait_over<R>(kp, polls, seen, t0)) return -1;
+    }
+}
+
+// Problem q enters `phase` with n items: its claims and finished items start from zero and
+// the queue is topped up to min(n, kp.tokens) of its tokens, with at most that many pushes
+// (other work-groups may pop them as fast as they come, so the count alone would not end
+// the loop).  A token still queued from an earlier phase counts: whoever pops it later
+// claims from the new phase word, which is stored before the count is read.  So the phase
+// always has a token coming (n > 0), a problem never holds more than kp.tokens queue slots,
+// and a problem's tokens, hence the claims beyond n in one phase, stay bounded.  One thread.
+template <typename R>
+__device__ void batch_start(const KParams<R> &kp, int q, int64_t phase, int n)
+{
+    SolveState &st = kp.solves[q];
+    st.done = 0;  // ordered before the phase word by the release below
+    __hip_atomic_store(&st.word, ((unsigned long long)phase << 40) | ((unsigned long long)n << 20),
+                       __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int want = n < kp.tokens ? n : kp.tokens;
+    for (int k = 0; k < want; ++k) {
+        const int had = __hip_atomic_fetch_add(&st.queued, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (had >= want) {
+            __hip_atomic_fetch_add(&st.queued, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        ring_push<R>(kp, q);
+    }
+}
+
+// The last item of problem q's `phase` is done (one thread, after an acquire): the next
+// phase, the next restart, or the end of the problem's solve.
+template <typename R>
+__device__ void batch_advance(const KParams<R> &kp, int q, int64_t phase)
+{
+    SolveState &st = kp.solves[q];
+    const int64_t r = phase / 2 + 1;
+    const int c = (int)(r & 1);
+    if ((phase & 1) == 0) {
+        // restart r's marching step is over; its march list is consumed
+        st.n_list[c] = 0;
+        for (int k = 0; k < 4; ++k) st.bin_n[c][k] = 0;
+        const int nx = st.x_n[c];
+        if (nx > 0) {
+            batch_start<R>(kp, q, phase + 1, nx);
+            return;
+        }
+    }
+    // restart r is over; its exchange list is consumed
+    st.x_n[c] = 0;
+    const int nn = st.n_list[c ^ 1];
+    if (nn == 0 || r >= kp.max_restarts) {
+        if (nn > 0) raise_error(kp.ctl, kErrRestarts);
+        st.r = (int)r;
+        st.finished = 1;
+        kp.prob_lastr[q] = (int)r - 1;  // restarts = this + 1, as in the shared loop
+        __hip_atomic_store(&st.word, (unsigned long long)(phase + 1) << 40, __ATOMIC_RELEASE,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&kp.ctl->remaining, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+    st.r = (int)r + 1;
+    batch_start<R>(kp, q, 2 * r, nn);  // the marching step of restart r + 1
+}
+
+template <typename R, int B, int W>
+__global__ void __launch_bounds__(64 * W)
+    __attribute__((amdgpu_waves_per_eu(Lds<R, B, W>::waves_per_simd))) k_batched(KParams<R> kp)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x;
+    Ctl *ctl = kp.ctl;
+    SolveState *S = kp.solves;
+    __shared__ int s_q;
+    __shared__ unsigned long long s_w;
+    __shared__ unsigned long long s_feat[9];  // no restart features in batches
+    if (tid < 9) s_feat[tid] = 0ull;
+    Totals tot;
+    FMM_CYC_DECL;
+    if (read_abort(ctl)) return;
+    int q = -1;
+    for (;;) {
+        if (q < 0) {
+            if (tid == 0) s_q = ring_pop<R>(kp);
+            __syncthreads();
+            q = s_q;
+            __syncthreads();
+            if (q < 0) break;
+            if (q >= kp.nprob) {  // a token that names no problem: stop, never index with it
+                if (tid == 0) raise_error(ctl, kErrList);
+                break;
+            }
+        }
+        if (tid == 0) {
+            s_w = __hip_atomic_fetch_add(&S[q].word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the phase's lists and counters
+        }
+        __syncthreads();
+        const unsigned long long wv = s_w;
+        __syncthreads();
+        const int64_t phase = (int64_t)(wv >> 40);
+        const int n = (int)((wv >> 20) & 0xFFFFFu), i = (int)(wv & 0xFFFFFu);
+        if (i >= n) {  // the phase has no item left: drop the token
+            q = -1;
+            continue;
+        }
+        const ProbDesc pd = kp.prob[q];
+        const int64_t r = phase / 2 + 1;
+        const int c = (int)(r & 1);
+        const ListSink sink{(c ? kp.list0 : kp.list1) + pd.blk0, S[q].bin_n[c ^ 1], &S[q].n_list[c ^ 1],
+                            kp.xlist + pd.blk0, &S[q].x_n[c], kp.nblk, pd.nblk};
+        bool bad = false;
+        if ((phase & 1) == 0) {
+            // marching step of restart r, item i: the bins in order, the most expected work first
+            const int32_t *cur = (c ? kp.list1 : kp.list0) + pd.blk0;
+            int k = 0, off = i;
+            while (k < 3 && off >= S[q].bin_n[c][k]) {
+                off -= S[q].bin_n[c][k];
+                ++k;
+            }
+            const int64_t ib = off < pd.nblk ? (int64_t)cur[(int64_t)k * kp.nblk + off] : -1;
+            if (ib < pd.blk0 || ib >= pd.blk0 + pd.nblk) {
+                bad = true;
+            } else {
+                const double bound = fixed_bound(r, pd.stride, pd.width);
+                ++tot.march_calls;
+                const R bm = kp.bmin[ib];
+                if ((double)bm > bound) {
+                    if (tid == 0) {
+                        if ((double)bm > pd.width) kp.A[ib] = 0;
+                        else {
+                            const int nbb = kp.band_n[ib];
+                            append_next<R>(kp, sink, r, ib, max(kp.lastpops[ib], nbb), nbb, s_feat);
+                        }
+                    }
+                } else {
+                    ++tot.tile_loads;
+                    bool a;
+                    int nbb, np;
+                    march_block<R, B, W>(kp, ib, pd, bound, sink, smem, tot.pops, a, nbb, np FMM_CYC_ARG);
+                    if (tid == 0 && a) append_next<R>(kp, sink, r, ib, max(np, nbb), nbb, s_feat);
+                }
+            }
+        } else {
+            // exchanging step of restart r, item i
+            const int64_t ib = kp.xlist[pd.blk0 + i];
+            if (ib < pd.blk0 || ib >= pd.blk0 + pd.nblk) {
+                bad = true;
+            } else {
+                const uint32_t cm = kp.Cm[ib];
+                const bool a0 = kp.A[ib] != 0;
+                bool an;
+                int nn;
+                exchange_block<R, B, W>(kp, ib, cm, pd, smem, an, nn);
+                ++tot.exchange_calls;
+                if (tid == 0 && an && !a0) append_next<R>(kp, sink, r, ib, max(kp.lastpops[ib], nn), nn, s_feat);
+            }
+        }
+        if (bad) {  // lists out of step with their counts: stop, never read past them
+            if (tid == 0) raise_error(ctl, kErrList);
+            break;
+        }
+        // the item is done; the work-group finishing the phase's last item moves q on
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const int d = __hip_atomic_fetch_add(&S[q].done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (d == n - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                batch_advance<R>(kp, q, phase);
+            }
+        }
+        __syncthreads();
+        if (read_abort(ctl)) break;
+    }
+    if (tid == 0) flush_totals(ctl, tot);
 }
 
 // ---------------------------------------------------------------- host-driven loop

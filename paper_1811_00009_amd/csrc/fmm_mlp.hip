@@ -221,6 +221,17 @@ int launch_loss_grad(const float *P, const float *X, const float *T, int64_t n, 
 
 } // namespace
 
+// Frees the scratch (on the device it was allocated on); the next use allocates again.
+void fmm_internal_mlp_release()
+{
+    float **bufs[5] = {&g_scr.partial, &g_scr.grad, &g_scr.m, &g_scr.v, &g_scr.loss};
+    for (float **b : bufs) {
+        if (*b) (void)hipFree(*b);
+        *b = nullptr;
+    }
+    g_scr.ok = false;
+}
+
 extern "C" {
 
 int fmm_mlp_forward(const float *params_dev, const float *x_dev, int64_t n, float *y_dev, void *hip_stream)

@@ -86,6 +86,11 @@ def main():
     for k, name in ((6, "tile, tags and band load to LDS (+ h^2/F^2 touch)"),
                     (7, "last Locate_Min, face test, tile store, flags")):
         lines.append(f"| {k}: {name} | {a[k] / max(marches, 1):.0f} | {per_pop[k]:.0f} |")
+    small, mid = a[14], a[15] - a[14]
+    lines.append("")
+    lines.append(f"Band size at the pick: {small / max(pops, 1) * 100:.1f} % of pops at most 64 slots, "
+                 f"{mid / max(pops, 1) * 100:.1f} % 65-256, "
+                 f"{(pops - a[15]) / max(pops, 1) * 100:.1f} % more than 256.")
     inst_pop_s = (sum(a[k] for k in range(8))) / hz / max(pops, 1)
     lines.append("")
     lines.append(f"Run: {st['pops']} pops, {marches} marches, {st['restarts']} restarts, loop "

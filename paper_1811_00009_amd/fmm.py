@@ -16,11 +16,14 @@ import os
 from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfmm_hip.so")
+# FMM_SANITIZE=1: the build with the host code under AddressSanitizer and UBSan
+# (build.py --sanitize; CPU tests with libasan preloaded)
+LIB_PATH = os.path.join(_HERE, "libfmm_hip_san.so" if os.environ.get("FMM_SANITIZE") == "1"
+                        else "libfmm_hip.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_ENOTSUP = 0, -1, -2, -3, -4, -5
 FMM_F32, FMM_F64 = 0, 1
-STRIDE_FIXED, STRIDE_LEARNED = 0, 1
+STRIDE_FIXED, STRIDE_LEARNED, STRIDE_SCHEDULE = 0, 1, 2
 LAUNCH_PERSISTENT, LAUNCH_HOST = 0, 1
 NFEAT = 12
 MLP_NPARAMS = 1505
@@ -41,7 +44,9 @@ class Options(C.Structure):
     _fields_ = [("width", C.c_double), ("stride_mode", C.c_int32), ("mlp_weights", C.c_void_p),
                 ("waves_per_block", C.c_int32), ("launch_mode", C.c_int32),
                 ("max_restarts", C.c_int64), ("grid_limit", C.c_int32),
-                ("trace_dev", C.c_void_p), ("trace_cap", C.c_int32), ("band_lds_cap", C.c_int32)]
+                ("trace_dev", C.c_void_p), ("trace_cap", C.c_int32), ("band_lds_cap", C.c_int32),
+                ("bounds", C.POINTER(C.c_double)), ("nbounds", C.c_int32),
+                ("per_problem_restarts", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -95,6 +100,13 @@ def load():
     lib.fmm_solve.argtypes = [i64, i64, i64, dbl, i32, vp, C.POINTER(Source), i32, i32, dbl, vp,
                               vp, C.POINTER(Options), C.POINTER(Stats)]
     lib.fmm_solve.restype = C.c_int
+    lib.fmm_solve_resume.argtypes = [i64, i64, i64, dbl, i32, vp, C.POINTER(Source), i32, i32,
+                                     dbl, vp, vp, C.POINTER(Options), i64, C.POINTER(Stats)]
+    lib.fmm_solve_resume.restype = C.c_int
+    lib.fmm_workspace_save.argtypes = [vp, C.c_size_t, C.POINTER(C.c_size_t), vp]
+    lib.fmm_workspace_save.restype = C.c_int
+    lib.fmm_workspace_restore.argtypes = [vp, C.c_size_t, vp]
+    lib.fmm_workspace_restore.restype = C.c_int
     lib.fmm_solve_noalloc.argtypes = [i64, i64, i64, dbl, i32, vp, C.POINTER(Source), i32, i32,
                                       dbl, vp, vp, C.POINTER(Options), C.POINTER(Stats)]
     lib.fmm_solve_noalloc.restype = C.c_int
@@ -121,7 +133,13 @@ def load():
     lib.fmm_last_error_detail.restype = C.c_char_p
     lib.fmm_version.argtypes = []
     lib.fmm_version.restype = C.c_char_p
+    lib.fmm_release.argtypes = []
+    lib.fmm_release.restype = C.c_int
     _lib = lib
+    # free the library's device memory and events before the interpreter (and with it the
+    # HIP runtime) shuts down; registered after torch's import, so it runs before torch's
+    import atexit
+    atexit.register(lib.fmm_release)
     return lib
 
 
@@ -163,11 +181,21 @@ def _sources(sources) -> "C.Array":
 
 def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_per_block=1,
                  launch="persistent", max_restarts=0, grid_limit=0, trace=None,
-                 band_lds_cap=0) -> Options:
+                 band_lds_cap=0, bounds=None, per_problem_restarts=False) -> Options:
+    """Options for a solve.  stride_mode: "fixed", "learned" (mlp_weights) or "schedule"
+    (bounds: the bound of each restart, then the last bound plus the stride)."""
     o = Options()
     load().fmm_options_default(C.byref(o))
     o.width = float(width)
-    o.stride_mode = STRIDE_LEARNED if stride_mode == "learned" else STRIDE_FIXED
+    modes = {"fixed": STRIDE_FIXED, "learned": STRIDE_LEARNED, "schedule": STRIDE_SCHEDULE}
+    if stride_mode not in modes:
+        raise ValueError(f"stride_mode must be one of {sorted(modes)}")
+    o.stride_mode = modes[stride_mode]
+    if bounds is not None:
+        arr = (C.c_double * len(bounds))(*[float(b) for b in bounds])
+        o._bounds_keep = arr  # the array lives as long as the options
+        o.bounds = C.cast(arr, C.POINTER(C.c_double))
+        o.nbounds = len(bounds)
     if mlp_weights is not None:
         import torch
         # the device reads MLP_BLOB_FLOATS float32 values through this pointer
@@ -183,6 +211,7 @@ def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_pe
     o.max_restarts = int(max_restarts)
     o.grid_limit = int(grid_limit)
     o.band_lds_cap = int(band_lds_cap)
+    o.per_problem_restarts = 1 if per_problem_restarts else 0
     if trace is not None:
         _check_tensor(trace, "trace")
         o.trace_dev = trace.data_ptr()
@@ -191,8 +220,10 @@ def make_options(width=math.inf, stride_mode="fixed", mlp_weights=None, waves_pe
 
 
 def solve(F, h: float, sources: Sequence, block: int = 16, stride: Optional[float] = None,
-          out=None, with_stats: bool = False, **opts):
-    """psi for speed F (GPU tensor (nz, ny, nx)) and point sources [(i, j, k[, psi0])]."""
+          out=None, with_stats: bool = False, stop_at_cap: bool = False, **opts):
+    """psi for speed F (GPU tensor (nz, ny, nx)) and point sources [(i, j, k[, psi0])].
+    stop_at_cap: a solve that reaches max_restarts returns (its stats get
+    "stopped_at_cap": True) instead of raising; psi is then incomplete."""
     import torch
     lib = load()
     _check_tensor(F, "F")
@@ -210,8 +241,64 @@ def solve(F, h: float, sources: Sequence, block: int = 16, stride: Optional[floa
     st = Stats()
     rc = lib.fmm_solve(nx, ny, nz, float(h), _dtype_code(F), F.data_ptr(), src, len(sources),
                        int(block), stride, out.data_ptr(), _stream(), C.byref(o), C.byref(st))
+    if stop_at_cap and rc == FMM_ENOCONV and b"restart cap" in lib.fmm_last_error_detail():
+        d = st.as_dict()
+        d["stopped_at_cap"] = True
+        return (out, d) if with_stats else out
     _check(rc, "fmm_solve")
     return (out, st.as_dict()) if with_stats else out
+
+
+def solve_resume(F, h: float, sources: Sequence, from_restart: int, block: int = 16,
+                 stride: Optional[float] = None, out=None, with_stats: bool = False,
+                 stop_at_cap: bool = False, **opts):
+    """Continue the solve of the same problem last stopped on this device at its restart
+    cap, from restart from_restart + 1 (fmm_solve_resume); arguments as solve()."""
+    import torch
+    lib = load()
+    _check_tensor(F, "F")
+    if F.dim() != 3:
+        raise ValueError("F must have shape (nz, ny, nx)")
+    nz, ny, nx = F.shape
+    if out is None:
+        out = torch.empty_like(F)
+    _check_tensor(out, "out")
+    if out.dtype != F.dtype or out.shape != F.shape:
+        raise ValueError("out must match F in shape and dtype")
+    stride = 2.0 * h if stride is None else float(stride)
+    o = make_options(**opts)
+    src = _sources(sources)
+    st = Stats()
+    rc = lib.fmm_solve_resume(nx, ny, nz, float(h), _dtype_code(F), F.data_ptr(), src,
+                              len(sources), int(block), stride, out.data_ptr(), _stream(),
+                              C.byref(o), int(from_restart), C.byref(st))
+    if stop_at_cap and rc == FMM_ENOCONV and b"restart cap" in lib.fmm_last_error_detail():
+        d = st.as_dict()
+        d["stopped_at_cap"] = True
+        return (out, d) if with_stats else out
+    _check(rc, "fmm_solve_resume")
+    return (out, st.as_dict()) if with_stats else out
+
+
+def workspace_save(buf=None):
+    """The state the last solve on this device left in the library workspace, copied into a
+    uint8 GPU tensor (buf, reused when large enough); see fmm_workspace_save."""
+    import torch
+    lib = load()
+    need = C.c_size_t(0)
+    _check(lib.fmm_workspace_save(None, 0, C.byref(need), _stream()), "fmm_workspace_save")
+    if buf is None or buf.numel() < need.value:
+        buf = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    _check(lib.fmm_workspace_save(buf.data_ptr(), buf.numel(), C.byref(need), _stream()),
+           "fmm_workspace_save")
+    buf._fmm_state_bytes = need.value
+    return buf
+
+
+def workspace_restore(buf):
+    """Copy a state saved by workspace_save back into the library workspace."""
+    n = getattr(buf, "_fmm_state_bytes", buf.numel())
+    _check(load().fmm_workspace_restore(buf.data_ptr(), n, _stream()), "fmm_workspace_restore")
 
 
 def solve_noalloc(F, h: float, sources: Sequence, out, block: int = 16,

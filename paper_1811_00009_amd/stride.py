@@ -123,6 +123,50 @@ def label_traces(traces_by_m: dict, rule: str = "field", nbins: int = 12, window
     return np.array(X, dtype=np.float32).reshape(-1, NFEAT), np.array(y, dtype=np.float32)
 
 
+def rollout_bounds(base_bounds: Sequence[float], r_d: int, m: float, s0: float,
+                   window: float) -> List[float]:
+    """Bound schedule of a rollout from decision restart r_d: the base solve's bounds of
+    restarts 1 .. r_d (the state after restart r_d is then the base solve's, bit for bit),
+    then a stride of m * s0 until the bound reaches bound_{r_d} + window."""
+    sched = [float(b) for b in base_bounds[:r_d]]
+    b0 = sched[-1]
+    j = 1
+    while True:
+        b = b0 + j * m * s0
+        sched.append(b)
+        if b >= b0 + window:
+            break
+        j += 1
+    return sched
+
+
+def window_seconds(rows, r_d: int, edge: float) -> float:
+    """Device seconds from the start of restart r_d + 1 until the end of the last later
+    restart that accepted a value at or below edge: the time the rollout took to make the
+    values below edge final."""
+    t0 = rows[r_d]["t_start"]
+    t_last = t0
+    for r in rows[r_d:]:
+        if r.get("min_popped", math.inf) <= edge:
+            t_last = max(t_last, r["t_end"])
+    return (t_last - t0) / TICKS_PER_S
+
+
+def label_rollouts(base_rows, costs_by_decision: dict):
+    """Samples of the rollout rule.  costs_by_decision: {r_d: {m: seconds}}; the sample of
+    decision r_d is the base solve's features at the end of restart r_d, and its target is
+    ln of the multiplier whose rollout made the next window of values final fastest."""
+    X, y = [], []
+    for r_d in sorted(costs_by_decision):
+        costs = costs_by_decision[r_d]
+        if not costs:
+            continue
+        m_best = min(costs, key=costs.get)
+        X.append(base_rows[r_d - 1]["feat"])
+        y.append(math.log(m_best))
+    return np.array(X, dtype=np.float32).reshape(-1, NFEAT), np.array(y, dtype=np.float32)
+
+
 def standardise(X: np.ndarray):
     mean = X.mean(axis=0)
     std = X.std(axis=0)

@@ -2,20 +2,25 @@
 
     python -m paper_1811_00009_amd.train_stride --fields 60 --out paper_1811_00009_amd/weights
 
-1. Traces: for each training field, one traced solve per fixed multiplier m in
-   stride.MULTIPLIERS (stride m * 2h); every restart records its features,
-   bound and device time.  Fields: coarse-cell speeds (64^3 cells, seeds (5, s),
-   n^3 grid); Fourier speeds (seeds (6, s)) and smooth sine speeds (seeds
-   (7, s)) can be mixed in (off by default: their fastest multipliers split
-   between ~1 and 4-8, and a regression on such labels lands in between, where
-   the solve is slowest).
-2. Labels per field: the multiplier whose whole solve took the least device time
-   (stride.label_traces).
-3. Full-batch training with the library's forward / backward / Adam kernels.
-4. Held-out evaluation on coarse-cell fields with seeds (50, s) at eval_n^3, and
+1. Labels.  The default rule ("rollout") labels restarts, not fields: for each
+   training field (coarse-cell speeds, 64^3 cells, seeds (5, s), n^3 grid) a base
+   solve at the fixed stride base_m * 2h is stopped at `decisions` restarts spread
+   over the solve; from each stopped state (saved and restored through the
+   library's workspace calls) every multiplier m in stride.MULTIPLIERS continues
+   with stride m * 2h until the bound has advanced by window_h * h, and the
+   restart's label is the m whose rollout made every value below that advance
+   final in the least device time (stride.label_rollouts).  The older rules
+   label every restart of a field with the multiplier whose whole fixed-stride
+   solve was fastest ("field") or per slab of the bound ("slab"); Fourier
+   (6, s) and sine (7, s) fields can be mixed into those.
+2. Full-batch training with the library's forward / backward / Adam kernels.
+3. Held-out evaluation on coarse-cell fields with seeds (50, s) at eval_n^3, and
    on a few unseen fields of the other families at n^3: device time of every
    fixed multiplier and of the learned stride, and psi of the learned solve
    against the fixed 2h solve (FP32 bar).
+
+Collection can be split over several runs: --collect-only with --first-field
+writes the samples of a range of fields, and --samples trains on such files.
 
 Writes <out>/stride_mlp_b<B>.f32 (the device blob: 1505 parameters, 12 feature
 means, 12 feature standard deviations, little-endian FP32) and
@@ -23,7 +28,7 @@ means, 12 feature standard deviations, little-endian FP32) and
 
     python -m paper_1811_00009_amd.train_stride --eval-only
 
-evaluates the blob already in <out> (step 4 only) and writes
+evaluates the blob already in <out> (step 3 only) and writes
 <out>/stride_mlp_b<B>.eval.json.
 """
 from __future__ import annotations
@@ -80,6 +85,80 @@ def collect(fmm, stride, torch, plan, n, block, rule, mults):
     return np.concatenate(Xs), np.concatenate(ys), best
 
 
+def rollout_field(fmm, stride, torch, p, F, block, mults, base_m, n_dec, window_h, extra):
+    """Rollout labels of one field.  The base solve (fixed stride base_m * 2h) is stopped
+    after each of n_dec decision restarts r_d; from that state (saved once, restored for
+    each rollout) every multiplier m continues with stride m * 2h until the bound has
+    advanced by window_h * h, then with the base stride for `extra` restarts; its cost is
+    the device time until the values below bound_{r_d} + window were final.  Returns
+    (X, y, costs) from stride.label_rollouts."""
+    s0 = 2 * p.h
+    base_stride = base_m * s0
+    window = window_h * p.h
+    _, st, rows = stride.trace_solve(fmm, F, p.h, p.sources, block=block, multiplier=base_m)
+    R = len(rows)
+    bounds = [r["bound"] for r in rows]
+    decisions = sorted(set(int(round(x)) for x in np.linspace(2, max(R - 3, 2), n_dec)))
+    out = torch.empty_like(F)
+    cap_rows = R + int(math.ceil(window / (min(mults) * s0))) + extra + 8
+    trace = torch.zeros(cap_rows * fmm.TRACE_ROW_BYTES, dtype=torch.uint8, device=F.device)
+    state = None
+    prev = 0
+    costs = {}
+    for r_d in decisions:
+        if r_d >= R:
+            break
+        # the base solve, stopped after restart r_d
+        if prev == 0:
+            _, sb = fmm.solve(F, p.h, p.sources, block=block, stride=base_stride, out=out,
+                              with_stats=True, max_restarts=r_d, stop_at_cap=True)
+        else:
+            fmm.workspace_restore(state)
+            _, sb = fmm.solve_resume(F, p.h, p.sources, prev, block=block, stride=base_stride,
+                                     out=out, with_stats=True, max_restarts=r_d,
+                                     stop_at_cap=True)
+        if not sb.get("stopped_at_cap"):
+            break  # the solve ended before r_d
+        state = fmm.workspace_save(state)
+        costs[r_d] = {}
+        for m in mults:
+            fmm.workspace_restore(state)
+            sched = stride.rollout_bounds(bounds, r_d, m, s0, window)
+            fmm.solve_resume(F, p.h, p.sources, r_d, block=block, stride=base_stride, out=out,
+                             stride_mode="schedule", bounds=sched, trace=trace,
+                             max_restarts=len(sched) + extra, stop_at_cap=True)
+            torch.cuda.synchronize()
+            rws = fmm.trace_rows(trace, min(len(sched) + extra, cap_rows))
+            last = max(i for i in range(len(rws)) if rws[i]["t_end"] > 0)
+            costs[r_d][m] = stride.window_seconds(rws[:last + 1], r_d, bounds[r_d - 1] + window)
+            trace.zero_()
+        prev = r_d
+    X, y = stride.label_rollouts(rows, costs)
+    return X, y, costs
+
+
+def collect_rollouts(fmm, stride, torch, fields, n, block, mults, base_m, n_dec, window_h,
+                     extra, first_seed=0):
+    """Rollout-labelled samples of coarse-cell training fields (seeds (5, s))."""
+    Xs, ys, picks, t0 = [], [], [], time.perf_counter()
+    for k, s in enumerate(range(first_seed, first_seed + fields)):
+        p, F = field([5, s], n, torch)
+        X, y, costs = rollout_field(fmm, stride, torch, p, F, block, mults, base_m, n_dec,
+                                    window_h, extra)
+        Xs.append(X)
+        ys.append(y)
+        picks.extend(round(math.exp(v), 4) for v in y)
+        if k % 10 == 0:
+            show = {r: min(c, key=c.get) for r, c in costs.items()}
+            log(f"field 5/{s}: {len(y)} decisions, picks {show}, "
+                f"{time.perf_counter() - t0:.0f} s")
+        del F
+    hist = {}
+    for m in picks:
+        hist[m] = hist.get(m, 0) + 1
+    return np.concatenate(Xs), np.concatenate(ys), hist
+
+
 def evaluate(fmm, stride, torch, blob_dev, seeds, n, block, mults=None):
     """Device time of every fixed multiplier (mults, default stride.MULTIPLIERS; 1.0, the
     fixed 2h, among them) and of the learned stride on the held-out fields `seeds` (seed
@@ -131,6 +210,8 @@ def run_evals(fmm, stride, torch, blob_dev, args):
         args.block, args.multipliers)}
     # unseen fields of the other families (seeds beyond the training range)
     for name, fam in (("fourier_unseen", 6), ("sine_unseen", 7)):
+        if args.other_eval_fields <= 0:
+            continue
         evals[name] = evaluate(fmm, stride, torch, blob_dev,
                                [[fam, 1000 + s] for s in range(args.other_eval_fields)],
                                args.n, args.block, args.multipliers)
@@ -144,9 +225,25 @@ def run_evals(fmm, stride, torch, blob_dev, args):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--fields", type=int, default=60, help="coarse-cell training fields")
+    ap.add_argument("--first-field", type=int, default=0,
+                    help="rollout rule: seed of the first training field (5, s)")
+    ap.add_argument("--collect-only", action="store_true",
+                    help="rollout rule: write the samples of fields [first, first + fields) "
+                         "to <out>/stride_samples_b<B>_<first>_<last>.npz and stop")
+    ap.add_argument("--samples", nargs="+", default=None,
+                    help="train on these sample files (from --collect-only) instead of "
+                         "collecting")
     ap.add_argument("--fourier-fields", type=int, default=0)
     ap.add_argument("--sine-fields", type=int, default=0)
-    ap.add_argument("--rule", default="field", choices=("field", "slab"))
+    ap.add_argument("--rule", default="rollout", choices=("rollout", "field", "slab"))
+    ap.add_argument("--base-multiplier", type=float, default=0.5,
+                    help="rollout rule: the fixed multiplier of the base solve")
+    ap.add_argument("--decisions", type=int, default=8,
+                    help="rollout rule: decision restarts per field")
+    ap.add_argument("--window-h", type=float, default=16.0,
+                    help="rollout rule: bound advance of a rollout, in h")
+    ap.add_argument("--extra", type=int, default=16,
+                    help="rollout rule: base-stride restarts after the window")
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--block", type=int, default=16)
     ap.add_argument("--steps", type=int, default=3000)
@@ -182,18 +279,46 @@ def main(argv=None):
             json.dump({"blob": os.path.basename(path), "eval": evals}, f, indent=1)
         return
     t0 = time.perf_counter()
-    plan = [(5, args.fields), (6, args.fourier_fields), (7, args.sine_fields)]
-    X, y, best = collect(fmm, stride, torch, plan, args.n, args.block, args.rule,
-                         args.multipliers)
-    hist = {}
-    for fam, _, m in best:
-        hist.setdefault(fam, {}).setdefault(m, 0)
-        hist[fam][m] += 1
-    log(f"{len(y)} samples in {time.perf_counter() - t0:.0f} s; fastest multiplier per "
-        f"family {hist}")
+    os.makedirs(args.out, exist_ok=True)
+    if args.samples:
+        parts = [np.load(f) for f in args.samples]
+        X = np.concatenate([q["X"] for q in parts])
+        y = np.concatenate([q["y"] for q in parts])
+        args.fields = int(sum(int(q["fields"]) for q in parts))
+        picks = {}
+        for v in y:
+            m = round(math.exp(float(v)), 4)
+            picks[m] = picks.get(m, 0) + 1
+        hist = {"5": picks}
+        log(f"{len(y)} samples of {args.fields} fields from {len(parts)} files; picks {picks}")
+    elif args.rule == "rollout":
+        X, y, picks = collect_rollouts(fmm, stride, torch, args.fields, args.n, args.block,
+                                       args.multipliers, args.base_multiplier, args.decisions,
+                                       args.window_h, args.extra, first_seed=args.first_field)
+        hist = {"5": picks}
+        log(f"{len(y)} samples in {time.perf_counter() - t0:.0f} s; rollout picks {picks}")
+        if args.collect_only:
+            last = args.first_field + args.fields
+            path = os.path.join(args.out, f"stride_samples_b{args.block}_{args.first_field}_{last}.npz")
+            np.savez(path, X=X, y=y, fields=args.fields, first=args.first_field, n=args.n,
+                     base_multiplier=args.base_multiplier, decisions=args.decisions,
+                     window_h=args.window_h, extra=args.extra)
+            log(f"wrote {path}")
+            return
+    else:
+        plan = [(5, args.fields), (6, args.fourier_fields), (7, args.sine_fields)]
+        X, y, best = collect(fmm, stride, torch, plan, args.n, args.block, args.rule,
+                             args.multipliers)
+        hist = {}
+        for fam, _, m in best:
+            hist.setdefault(fam, {}).setdefault(m, 0)
+            hist[fam][m] += 1
+        log(f"{len(y)} samples in {time.perf_counter() - t0:.0f} s; fastest multiplier per "
+            f"family {hist}")
+    if not args.samples:
+        np.savez(os.path.join(args.out, f"stride_samples_b{args.block}.npz"), X=X, y=y)
     blob, params, lh = stride.train(fmm, X, y, steps=args.steps, lr=args.lr)
     log(f"loss {lh[0]:.4f} -> {lh[-1]:.4f} after {args.steps} steps")
-    os.makedirs(args.out, exist_ok=True)
     path = os.path.join(args.out, f"stride_mlp_b{args.block}.f32")
     blob.astype("<f4").tofile(path)
     blob_dev = torch.from_numpy(blob.astype(np.float32)).cuda()
@@ -204,6 +329,9 @@ def main(argv=None):
                                 "fourier (6, s)": args.fourier_fields,
                                 "sine (7, s)": args.sine_fields},
                      "n": args.n, "rule": args.rule, "fastest_multiplier_per_family": hist,
+                     "rollout": {"base_multiplier": args.base_multiplier,
+                                 "decisions_per_field": args.decisions,
+                                 "window_h": args.window_h, "extra_restarts": args.extra},
                      "block": args.block, "multipliers": list(args.multipliers),
                      "samples": int(len(y)), "steps": args.steps, "lr": args.lr,
                      "loss_first": float(lh[0]), "loss_last": float(lh[-1])},

@@ -38,7 +38,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(fmm.Source) == 32
     assert C.sizeof(fmm.TraceRow) == 48 + 8 * 5 + 8 + 8
     assert C.sizeof(fmm.Stats) == 5 * 8 + 3 * 8 + 4 * 4
-    assert C.sizeof(fmm.Options) == 64
+    assert C.sizeof(fmm.Options) == 80
 
 
 def test_options_default():
@@ -65,7 +65,7 @@ def _solve_raw(nx=16, ny=16, nz=16, h=0.1, dtype=0, F=1, srcs=((1, 1, 1, 0.0),),
     (dict(stride=0.0), fmm.FMM_EINVAL),
     (dict(stride=-1.0), fmm.FMM_EINVAL),
     (dict(stride=float("nan")), fmm.FMM_EINVAL),
-    (dict(block=32), fmm.FMM_ENOTSUP),
+    (dict(block=64), fmm.FMM_ENOTSUP),
     (dict(block=5), fmm.FMM_ENOTSUP),
     (dict(nx=20), fmm.FMM_EINVAL),          # not divisible by the block
     (dict(F=0), fmm.FMM_EINVAL),            # NULL speed
@@ -95,6 +95,38 @@ def test_validation_rejects_bad_options():
     fmm.load().fmm_options_default(C.byref(o))
     o.stride_mode = fmm.STRIDE_LEARNED
     assert _solve_raw(stride=float("inf"), opt=o) == fmm.FMM_EINVAL
+
+
+def test_bound_schedule_is_checked_on_the_host():
+    """FMM_STRIDE_SCHEDULE needs a host array of finite, positive, non-decreasing bounds."""
+    def opts(bounds, n=None):
+        o = fmm.Options()
+        fmm.load().fmm_options_default(C.byref(o))
+        o.stride_mode = fmm.STRIDE_SCHEDULE
+        if bounds is not None:
+            arr = (C.c_double * len(bounds))(*bounds)
+            o._keep = arr
+            o.bounds = C.cast(arr, C.POINTER(C.c_double))
+        o.nbounds = len(bounds) if n is None else n
+        return o
+    assert _solve_raw(opt=opts(None, 3)) == fmm.FMM_EINVAL
+    assert _solve_raw(opt=opts([0.1, 0.2], 0)) == fmm.FMM_EINVAL
+    assert _solve_raw(opt=opts([0.2, 0.1])) == fmm.FMM_EINVAL        # decreasing
+    assert _solve_raw(opt=opts([0.0, 0.1])) == fmm.FMM_EINVAL        # not > 0
+    assert _solve_raw(opt=opts([0.1, float("inf")])) == fmm.FMM_EINVAL
+    assert _solve_raw(opt=opts([0.1, 0.2]), stride=float("inf")) == fmm.FMM_EINVAL
+    with pytest.raises(ValueError):
+        fmm.make_options(stride_mode="adaptive")
+
+
+def test_block_32_takes_one_wave_per_block():
+    """32^3 blocks march their tile in device memory with one wave; more waves are refused
+    before any device work."""
+    o = fmm.Options()
+    fmm.load().fmm_options_default(C.byref(o))
+    o.waves_per_block = 2
+    assert _solve_raw(nx=32, ny=32, nz=32, block=32, opt=o) == fmm.FMM_ENOTSUP
+    assert "one wave" in fmm.load().fmm_last_error_detail().decode()
 
 
 def test_strerror_covers_codes():

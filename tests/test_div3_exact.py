@@ -1,11 +1,13 @@
-"""The FP32 division by 3 of the upwind solve (div3 in fmm_device.hpp) is the IEEE
-quotient for every finite binary32 input.
+"""The FP32 divisions by k = 1, 2, 3 of the upwind solve (div_k in fmm_device.hpp) are
+the IEEE quotient for every finite binary32 input.
 
-div3 takes q0 = x * RN(1/3), the exact residual r = fma(-3, q0, x) and returns
-fma(r, RN(1/3), q0).  This test runs that sequence over all 2^31 non-negative binary32
-values, denormals included, in C on the host (IEEE binary32 arithmetic with true fused
-multiply-adds, as on the device with its FP32 denormals on) and compares every result
-bit for bit with x / 3.  The rounding is odd-symmetric, so negative inputs follow.
+div_k takes q0 = x * c_k with c_k = 1, 1/2, RN(1/3), the exact residual
+r = fma(-k, q0, x) and returns fma(r, c_k, q0).  For k = 1 and 2 the product is the
+correctly rounded quotient already and the correction leaves it unchanged; for k = 3 the
+correction makes it so.  This test runs that sequence over all 2^31 non-negative binary32
+values, denormals included, for each k, in C on the host (IEEE binary32 arithmetic with
+true fused multiply-adds, as on the device with its FP32 denormals on) and compares every
+result bit for bit with x / k.  The rounding is odd-symmetric, so negative inputs follow.
 """
 import os
 import platform
@@ -21,16 +23,19 @@ SRC = r"""
 static float f(uint32_t u) { float x; memcpy(&x, &u, 4); return x; }
 static uint32_t b(float x) { uint32_t u; memcpy(&u, &x, 4); return u; }
 int main(void) {
-    const float c = f(0x3eaaaaabu);
     if (b(1.0f / 3.0f) != 0x3eaaaaabu) return 2;
+    const float cs[3] = {1.0f, 0.5f, f(0x3eaaaaabu)};
     long long bad = 0;
+    for (int k = 1; k <= 3; ++k) {
+        const float c = cs[k - 1], kf = (float)k;
 #pragma omp parallel for reduction(+ : bad) schedule(static, 1 << 20)
-    for (long long u = 0; u < 0x7f800000LL; ++u) {
-        const float x = f((uint32_t)u);
-        const float q0 = x * c;
-        const float r = __builtin_fmaf(-3.0f, q0, x);
-        const float q1 = __builtin_fmaf(r, c, q0);
-        if (b(q1) != b(x / 3.0f)) ++bad;
+        for (long long u = 0; u < 0x7f800000LL; ++u) {
+            const float x = f((uint32_t)u);
+            const float q0 = x * c;
+            const float r = __builtin_fmaf(-kf, q0, x);
+            const float q1 = __builtin_fmaf(r, c, q0);
+            if (b(q1) != b(x / kf)) ++bad;
+        }
     }
     printf("%lld\n", bad);
     return bad != 0;
@@ -40,7 +45,7 @@ int main(void) {
 
 @pytest.mark.skipif(shutil.which("gcc") is None or platform.machine() not in ("x86_64", "AMD64"),
                     reason="needs gcc on x86-64 (-mfma)")
-def test_div3_is_the_ieee_quotient_for_all_binary32(tmp_path):
+def test_div_k_is_the_ieee_quotient_for_all_binary32(tmp_path):
     src = tmp_path / "div3.c"
     exe = tmp_path / "div3"
     src.write_text(SRC)

@@ -26,13 +26,15 @@ def _problems(dtype):
     return probs
 
 
+@pytest.mark.parametrize("per_problem", [False, True])
 @pytest.mark.parametrize("dtype,block", [(np.float32, 8), (np.float64, 16), (np.float32, 16)])
-def test_batch_equals_individual_solves_and_reference(fmm_lib, dtype, block):
+def test_batch_equals_individual_solves_and_reference(fmm_lib, dtype, block, per_problem):
     import torch
     probs = _problems(dtype)
     Fs = [torch.from_numpy(p.F).cuda() for p in probs]
     outs, stats = fmm_lib.solve_batched([(F, p.h, p.sources, p.stride) for F, p in zip(Fs, probs)],
-                                        block=block, with_stats=True)
+                                        block=block, with_stats=True,
+                                        per_problem_restarts=per_problem)
     for F, p, o, st in zip(Fs, probs, outs, stats):
         single, s1 = fmm_lib.solve(F, p.h, p.sources, block=block, stride=p.stride,
                                    with_stats=True)
@@ -75,3 +77,26 @@ def test_autotune_picks_a_supported_pair_and_caches(fmm_lib, tmp_path):
         ref = oracle.block_fmm(p.F, p.h, p.sources, block=t["block"], stride=2 * p.h,
                                dtype=np.float32)
         assert np.array_equal(o.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("block,waves", [(8, 1), (16, 1), (8, 2)])
+def test_per_problem_restarts_on_many_uneven_problems(fmm_lib, block, waves):
+    """64 problems of uneven sizes and strides, each restarting on its own in one launch:
+    every psi and every problem's restart and pop counts equal its own solve's."""
+    import torch
+    rng = np.random.default_rng(block + waves)
+    batch, probs = [], []
+    for s in range(64):
+        shape = tuple(int(v) for v in rng.choice([16, 32, 48, 64], size=3))
+        p = inputs.random_problem(700 + s, shape=shape, nsrc=1 + s % 2, dtype=np.float32,
+                                  obstacles=0.02 if s % 3 == 0 else 0.0)
+        p.stride = float(rng.choice([0.5, 1.0, 2.0, 3.5])) * p.h
+        probs.append(p)
+        batch.append((torch.from_numpy(p.F).cuda(), p.h, p.sources, p.stride))
+    outs, stats = fmm_lib.solve_batched(batch, block=block, waves_per_block=waves, with_stats=True,
+                                        per_problem_restarts=True)
+    for (F, h, src, stride), o, st in zip(batch, outs, stats):
+        single, s1 = fmm_lib.solve(F, h, src, block=block, stride=stride, with_stats=True,
+                                   waves_per_block=waves)
+        assert torch.equal(o, single)
+        assert st["restarts"] == s1["restarts"] and st["pops"] == s1["pops"]

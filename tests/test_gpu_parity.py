@@ -325,3 +325,23 @@ def test_paper_cases_fp64(fmm_lib, case):
     assert restarts[0] > restarts[1] > restarts[2]
     if case == 4:
         assert np.isinf(base).any()  # points inside the barriers stay unreached
+
+
+# ------------------------------------------------------------------ 32^3 blocks
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("shape,seed", [((64, 64, 64), 320), ((96, 64, 128), 321)])
+def test_block_32_is_bitwise_the_block_reference(fmm_lib, dtype, shape, seed):
+    """The paper's best parallel block size (Sec. 3.6): 32^3 blocks, marched in device
+    memory by one wave, equal the Alg. 6 block reference bitwise (psi, restarts, pops,
+    march and exchange calls) and the single-heap baseline to the bar; also with the band
+    past 512 register slots kept in memory."""
+    p = inputs.random_problem(seed, shape=shape, nsrc=3, obstacles=0.02, dtype=dtype)
+    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=32, stride=2 * p.h, dtype=dtype,
+                               stats=True)
+    base = oracle.fmm(p.F, p.h, p.sources, dtype=dtype)
+    for cap in (0, 512):
+        got, st = _run(fmm_lib, p, dtype, block=32, stride=2 * p.h, band_lds_cap=cap)
+        assert np.array_equal(got, ref), cap
+        for k in ("restarts", "pops", "march_calls", "exchange_calls"):
+            assert st[k] == rs[k], (cap, k, st[k], rs[k])
+        _assert_fp_parity(got, base, dtype)

@@ -106,6 +106,79 @@ def test_learned_stride_replays_bitwise_on_block_reference(fmm_lib, dtype):
         assert rows[r + 1]["stride_used"] == pytest.approx(m * 2 * p.h, rel=1e-5)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_bound_schedule_replays_bitwise_on_block_reference(fmm_lib, dtype):
+    """A given bound sequence (irregular, with repeats, then the stride after it) gives
+    bitwise the block reference run on the same sequence; the trace shows the bounds, and
+    a solve stopped at the restart cap reports it instead of failing."""
+    p = inputs.random_problem(605, shape=(40, 32, 24), nsrc=2, dtype=dtype, obstacles=0.02)
+    F = _t(p.F)
+    rng = np.random.default_rng(7)
+    bounds = np.cumsum(rng.choice([0.0, 0.5, 1.0, 3.0], size=30) * p.h) + 0.5 * p.h
+    trace = torch_zeros_trace(400)
+    psi, st = fmm_lib.solve(F, p.h, p.sources, block=8, stride=2 * p.h, with_stats=True,
+                            stride_mode="schedule", bounds=list(bounds), trace=trace)
+    got = psi.cpu().numpy()
+    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=8, stride=2 * p.h, bounds=bounds,
+                               dtype=dtype, stats=True)
+    assert np.array_equal(got, ref)
+    assert rs["restarts"] == st["restarts"] and rs["pops"] == st["pops"]
+    rows = fmm_lib.trace_rows(trace, min(st["restarts"], 400))
+    for r, row in enumerate(rows[:len(bounds)]):
+        assert row["bound"] == bounds[r]
+    if len(rows) > len(bounds):
+        assert rows[len(bounds)]["bound"] == pytest.approx(bounds[-1] + 2 * p.h, rel=1e-12)
+    cap = max(2, st["restarts"] // 2)
+    _, sc = fmm_lib.solve(F, p.h, p.sources, block=8, stride=2 * p.h, with_stats=True,
+                          stride_mode="schedule", bounds=list(bounds), max_restarts=cap,
+                          stop_at_cap=True)
+    assert sc.get("stopped_at_cap") and sc["restarts"] == cap
+
+
+@pytest.mark.parametrize("block", [8, 16])
+def test_stop_resume_and_saved_state_continue_exactly(fmm_lib, block):
+    """A solve stopped at its restart cap and resumed, and two continuations from one saved
+    state (one with another bound schedule that rejoins the same bounds), each give bitwise
+    the uninterrupted solve's psi, and their restart and pop counts add up."""
+    import torch
+    p = inputs.random_problem(606, shape=(48, 48, 32), nsrc=2, dtype=np.float32, obstacles=0.02)
+    F = _t(p.F)
+    s = 2 * p.h
+    full, sf = fmm_lib.solve(F, p.h, p.sources, block=block, stride=s, with_stats=True)
+    k = max(2, sf["restarts"] // 3)
+    part, sp = fmm_lib.solve(F, p.h, p.sources, block=block, stride=s, with_stats=True,
+                             max_restarts=k, stop_at_cap=True)
+    assert sp["stopped_at_cap"] and sp["restarts"] == k
+    state = fmm_lib.workspace_save()
+    rest, sr = fmm_lib.solve_resume(F, p.h, p.sources, k, block=block, stride=s, with_stats=True)
+    assert torch.equal(rest, full)
+    assert sr["restarts"] == sf["restarts"] and sp["pops"] + sr["pops"] == sf["pops"]
+    # the same state again, continued through a bound schedule: the fixed bounds up to k,
+    # then smaller steps, then the fixed stride from the last scheduled bound
+    fmm_lib.workspace_restore(state)
+    sched = [r * s for r in range(1, k + 1)] + [k * s + 0.5 * s * j for j in range(1, 5)]
+    alt, sa = fmm_lib.solve_resume(F, p.h, p.sources, k, block=block, stride=s, with_stats=True,
+                                   stride_mode="schedule", bounds=sched)
+    ref, rs = oracle.block_fmm(p.F, p.h, p.sources, block=block, stride=s, bounds=np.array(sched),
+                               dtype=np.float32, stats=True)
+    assert np.array_equal(alt.cpu().numpy(), ref)
+    assert sp["pops"] + sa["pops"] == rs["pops"] and sa["restarts"] == rs["restarts"]
+    # a resume of another problem is refused
+    G = _t(inputs.random_problem(607, shape=(48, 48, 32), nsrc=1, dtype=np.float32).F)
+    with pytest.raises(fmm_lib.FmmError):
+        fmm_lib.solve_resume(G, p.h, [(1, 2, 3, 0.0)], k, block=block, stride=s)
+
+
+def torch_zeros_trace(rows):
+    import torch
+    return torch.zeros(rows * fmm_lib_row_bytes(), dtype=torch.uint8, device="cuda")
+
+
+def fmm_lib_row_bytes():
+    from paper_1811_00009_amd import fmm
+    return fmm.TRACE_ROW_BYTES
+
+
 def test_learned_stride_falls_back_without_usable_weights(fmm_lib):
     import torch
     p = inputs.random_problem(601, shape=(24, 24, 24), nsrc=1)
