@@ -23,7 +23,7 @@ SEGMENTS = [
     (1, "psi gather of the slots and per-lane minimum"),
     (2, "cross-lane minimum and key (DPP, permlane swaps, ballot, readlane)"),
     (3, "bound test, neighbour tag/psi reads, Remove_Min, retag of p"),
-    (4, "the six neighbour solves (Alg. 2-3), lanes 0-5"),
+    (4, "the six neighbour solves (Alg. 2-3), quads 0-5"),
     (5, "insert (ballot, append) and loop back"),
 ]
 LANE0 = [

@@ -152,19 +152,35 @@ def window_seconds(rows, r_d: int, edge: float) -> float:
     return (t_last - t0) / TICKS_PER_S
 
 
-def label_rollouts(base_rows, costs_by_decision: dict):
+def pick_multiplier(costs: dict, tol: float = 0.0) -> float:
+    """The label of one decision: the multiplier of least cost, or with tol > 0 the
+    largest multiplier whose cost is within (1 + tol) of the least (fewer restarts among
+    rollouts that the timing cannot tell apart)."""
+    c_min = min(costs.values())
+    return max(m for m, c in costs.items() if c <= (1.0 + tol) * c_min)
+
+
+def label_rollouts(base_rows, costs_by_decision: dict, mults: Sequence[float] = None,
+                   tol: float = 0.0):
     """Samples of the rollout rule.  costs_by_decision: {r_d: {m: seconds}}; the sample of
     decision r_d is the base solve's features at the end of restart r_d, and its target is
-    ln of the multiplier whose rollout made the next window of values final fastest."""
-    X, y = [], []
+    ln of the multiplier whose rollout made the next window of values final fastest
+    (pick_multiplier).  Returns (X, y, C, R): C holds each sample's costs in the order of
+    mults (default: sorted multipliers of the first decision), R its decision restart."""
+    X, y, C, R = [], [], [], []
     for r_d in sorted(costs_by_decision):
         costs = costs_by_decision[r_d]
         if not costs:
             continue
-        m_best = min(costs, key=costs.get)
+        if mults is None:
+            mults = sorted(costs)
         X.append(base_rows[r_d - 1]["feat"])
-        y.append(math.log(m_best))
-    return np.array(X, dtype=np.float32).reshape(-1, NFEAT), np.array(y, dtype=np.float32)
+        y.append(math.log(pick_multiplier(costs, tol)))
+        C.append([costs.get(m, math.inf) for m in mults])
+        R.append(r_d)
+    nm = len(mults) if mults is not None else 0
+    return (np.array(X, dtype=np.float32).reshape(-1, NFEAT), np.array(y, dtype=np.float32),
+            np.array(C, dtype=np.float64).reshape(-1, nm), np.array(R, dtype=np.int32))
 
 
 def standardise(X: np.ndarray):

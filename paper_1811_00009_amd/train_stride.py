@@ -91,7 +91,8 @@ def rollout_field(fmm, stride, torch, p, F, block, mults, base_m, n_dec, window_
     each rollout) every multiplier m continues with stride m * 2h until the bound has
     advanced by window_h * h, then with the base stride for `extra` restarts; its cost is
     the device time until the values below bound_{r_d} + window were final.  Returns
-    (X, y, costs) from stride.label_rollouts."""
+    (X, y, C, R, costs): samples, rollout costs and decision restarts from
+    stride.label_rollouts, and the costs by decision."""
     s0 = 2 * p.h
     base_stride = base_m * s0
     window = window_h * p.h
@@ -133,20 +134,25 @@ def rollout_field(fmm, stride, torch, p, F, block, mults, base_m, n_dec, window_
             costs[r_d][m] = stride.window_seconds(rws[:last + 1], r_d, bounds[r_d - 1] + window)
             trace.zero_()
         prev = r_d
-    X, y = stride.label_rollouts(rows, costs)
-    return X, y, costs
+    X, y, C, R = stride.label_rollouts(rows, costs, mults)
+    return X, y, C, R, costs
 
 
 def collect_rollouts(fmm, stride, torch, fields, n, block, mults, base_m, n_dec, window_h,
                      extra, first_seed=0):
-    """Rollout-labelled samples of coarse-cell training fields (seeds (5, s))."""
-    Xs, ys, picks, t0 = [], [], [], time.perf_counter()
+    """Rollout-labelled samples of coarse-cell training fields (seeds (5, s)): features,
+    targets, each sample's rollout costs (seconds, in the order of mults), its decision
+    restart and its field seed, and the histogram of the picked multipliers."""
+    Xs, ys, Cs, Rs, Ss, picks, t0 = [], [], [], [], [], [], time.perf_counter()
     for k, s in enumerate(range(first_seed, first_seed + fields)):
         p, F = field([5, s], n, torch)
-        X, y, costs = rollout_field(fmm, stride, torch, p, F, block, mults, base_m, n_dec,
-                                    window_h, extra)
+        X, y, C, R, costs = rollout_field(fmm, stride, torch, p, F, block, mults, base_m,
+                                          n_dec, window_h, extra)
         Xs.append(X)
         ys.append(y)
+        Cs.append(C)
+        Rs.append(R)
+        Ss.append(np.full(len(y), s, dtype=np.int32))
         picks.extend(round(math.exp(v), 4) for v in y)
         if k % 10 == 0:
             show = {r: min(c, key=c.get) for r, c in costs.items()}
@@ -156,7 +162,8 @@ def collect_rollouts(fmm, stride, torch, fields, n, block, mults, base_m, n_dec,
     hist = {}
     for m in picks:
         hist[m] = hist.get(m, 0) + 1
-    return np.concatenate(Xs), np.concatenate(ys), hist
+    return (np.concatenate(Xs), np.concatenate(ys), hist,
+            {"C": np.concatenate(Cs), "R": np.concatenate(Rs), "S": np.concatenate(Ss)})
 
 
 def evaluate(fmm, stride, torch, blob_dev, seeds, n, block, mults=None):
@@ -233,6 +240,10 @@ def main(argv=None):
     ap.add_argument("--samples", nargs="+", default=None,
                     help="train on these sample files (from --collect-only) instead of "
                          "collecting")
+    ap.add_argument("--label-tol", type=float, default=0.0,
+                    help="with --samples: relabel every sample with the largest multiplier "
+                         "whose rollout cost is within (1 + tol) of the least "
+                         "(stride.pick_multiplier); files without costs are left out")
     ap.add_argument("--fourier-fields", type=int, default=0)
     ap.add_argument("--sine-fields", type=int, default=0)
     ap.add_argument("--rule", default="rollout", choices=("rollout", "field", "slab"))
@@ -282,8 +293,21 @@ def main(argv=None):
     os.makedirs(args.out, exist_ok=True)
     if args.samples:
         parts = [np.load(f) for f in args.samples]
+        if args.label_tol > 0:
+            kept = [q for q in parts if "C" in q.files]
+            if len(kept) < len(parts):
+                log(f"{len(parts) - len(kept)} sample files without rollout costs left out")
+            parts = kept
+            for q in parts:
+                if list(q["multipliers"]) != list(args.multipliers):
+                    raise SystemExit("sample files were collected with other multipliers")
         X = np.concatenate([q["X"] for q in parts])
-        y = np.concatenate([q["y"] for q in parts])
+        if args.label_tol > 0:
+            y = np.concatenate([[math.log(stride.pick_multiplier(dict(zip(args.multipliers, c)),
+                                                                 args.label_tol))
+                                 for c in q["C"]] for q in parts]).astype(np.float32)
+        else:
+            y = np.concatenate([q["y"] for q in parts])
         args.fields = int(sum(int(q["fields"]) for q in parts))
         picks = {}
         for v in y:
@@ -292,17 +316,20 @@ def main(argv=None):
         hist = {"5": picks}
         log(f"{len(y)} samples of {args.fields} fields from {len(parts)} files; picks {picks}")
     elif args.rule == "rollout":
-        X, y, picks = collect_rollouts(fmm, stride, torch, args.fields, args.n, args.block,
-                                       args.multipliers, args.base_multiplier, args.decisions,
-                                       args.window_h, args.extra, first_seed=args.first_field)
+        X, y, picks, meta = collect_rollouts(fmm, stride, torch, args.fields, args.n,
+                                             args.block, args.multipliers,
+                                             args.base_multiplier, args.decisions,
+                                             args.window_h, args.extra,
+                                             first_seed=args.first_field)
         hist = {"5": picks}
         log(f"{len(y)} samples in {time.perf_counter() - t0:.0f} s; rollout picks {picks}")
         if args.collect_only:
             last = args.first_field + args.fields
             path = os.path.join(args.out, f"stride_samples_b{args.block}_{args.first_field}_{last}.npz")
-            np.savez(path, X=X, y=y, fields=args.fields, first=args.first_field, n=args.n,
-                     base_multiplier=args.base_multiplier, decisions=args.decisions,
-                     window_h=args.window_h, extra=args.extra)
+            np.savez(path, X=X, y=y, C=meta["C"], R=meta["R"], S=meta["S"],
+                     multipliers=np.array(args.multipliers), fields=args.fields,
+                     first=args.first_field, n=args.n, base_multiplier=args.base_multiplier,
+                     decisions=args.decisions, window_h=args.window_h, extra=args.extra)
             log(f"wrote {path}")
             return
     else:
@@ -328,7 +355,9 @@ def main(argv=None):
            "train": {"fields": {"coarse_cells (5, s)": args.fields,
                                 "fourier (6, s)": args.fourier_fields,
                                 "sine (7, s)": args.sine_fields},
-                     "n": args.n, "rule": args.rule, "fastest_multiplier_per_family": hist,
+                     "n": args.n, "rule": args.rule, "label_tol": args.label_tol,
+                     "sample_files": [os.path.basename(f) for f in (args.samples or [])],
+                     "fastest_multiplier_per_family": hist,
                      "rollout": {"base_multiplier": args.base_multiplier,
                                  "decisions_per_field": args.decisions,
                                  "window_h": args.window_h, "extra_restarts": args.extra},

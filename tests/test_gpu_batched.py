@@ -65,7 +65,7 @@ def test_autotune_picks_a_supported_pair_and_caches(fmm_lib, tmp_path):
     samples = [(torch.from_numpy(p.F).cuda(), p.h, p.sources) for p in probs]
     cache = str(tmp_path / "tune.txt")
     t = fmm_lib.autotune(samples, cache_path=cache)
-    assert t["block"] in (8, 16) and t["waves_per_block"] in (1, 2, 4) and t["ms"] > 0
+    assert t["block"] in (8, 16, 32) and t["waves_per_block"] in (1, 2, 4) and t["ms"] > 0
     assert os.path.exists(cache)
     line = open(cache).read().split()
     assert int(line[1]) == t["block"] and int(line[2]) == t["waves_per_block"]

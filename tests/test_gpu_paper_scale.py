@@ -28,7 +28,7 @@ def _log(msg):
 
 def _gpu_solve(fmm, p, block):
     import torch
-    F = torch.from_numpy(p.F).cuda()
+    F = torch.from_numpy(np.array(p.F)).cuda()  # a writable copy (case 1's F is a broadcast)
     psi, st = fmm.solve(F, p.h, p.sources, block=block, stride=2 * p.h, with_stats=True)
     torch.cuda.synchronize()
     out = psi.cpu().numpy()

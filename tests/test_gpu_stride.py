@@ -225,7 +225,8 @@ def _trained_blob():
 def test_trained_network_keeps_psi_and_beats_fixed_2h(fmm_lib):
     """The committed network on an unseen coarse-cell field (the training family, 256^3):
     psi stays within the FP32 bar of the fixed-stride solve and of the single-heap oracle
-    (on a box around the source), and the solve is faster than the plain 2h stride."""
+    (on a box around the source), the solve is faster than the plain 2h stride, and the
+    stride changes from restart to restart."""
     import torch
     from boxcut import box_origin, box_slices, exact_region
     blob = _trained_blob()
@@ -252,3 +253,7 @@ def test_trained_network_keeps_psi_and_beats_fixed_2h(fmm_lib):
     # the gain: fewer device milliseconds than the method with its default stride
     assert min(learned_ms) < min(fixed_ms), (learned_ms, fixed_ms)
     assert sl["restarts"] != sf["restarts"]  # the network did choose other strides
+    # and not one stride for the whole solve: the multiplier follows the restart features
+    _, st, rows = stride_mod.trace_solve(fmm_lib, F, p.h, p.sources, block=16, blob=blob)
+    used = {round(r["stride_used"] / p.h, 4) for r in rows[:-1]}  # the last is cut by the width
+    assert len(used) > 1, used

@@ -426,6 +426,34 @@ def test_adam_step_matches_closed_form_first_step():
 
 
 # ----------------------------------------------------------------------- stride labels (host logic)
+def test_rollout_schedule_window_cost_and_labels():
+    """Rollout rule: the schedule repeats the base bounds up to the decision restart, then
+    steps by m * s0 until the window is covered; a rollout's cost runs from the restart
+    after the decision to the end of the last restart that accepted a value inside the
+    window; the label is the cheapest multiplier, or with a tolerance the largest one
+    within it, and each sample keeps its costs in multiplier order."""
+    from paper_1811_00009_amd import stride as stride_mod
+    base = [0.1, 0.2, 0.3, 0.4]
+    sched = stride_mod.rollout_bounds(base, 2, 0.5, 0.2, 0.35)
+    assert sched[:2] == [0.1, 0.2] and np.allclose(sched[2:], [0.3, 0.4, 0.5, 0.6])
+    rows = [{"t_start": 0, "t_end": 100, "min_popped": 0.0},
+            {"t_start": 100, "t_end": 300, "min_popped": 0.25},
+            {"t_start": 300, "t_end": 700, "min_popped": 0.45},
+            {"t_start": 700, "t_end": 900, "min_popped": 0.31}]  # a late correction at 0.31
+    assert stride_mod.window_seconds(rows, 1, 0.35) == pytest.approx(800 / stride_mod.TICKS_PER_S)
+    assert stride_mod.window_seconds(rows, 1, 0.30) == pytest.approx(200 / stride_mod.TICKS_PER_S)
+    feats = [{"feat": np.full(12, k, np.float32)} for k in range(8)]
+    costs = {3: {0.25: 1.00, 0.5: 1.01, 1.0: 1.30}, 6: {0.25: 1.20, 0.5: 1.00, 1.0: 1.05}}
+    X, y, C, R = stride_mod.label_rollouts(feats, costs, (0.25, 0.5, 1.0))
+    assert np.allclose(np.exp(y), [0.25, 0.5]) and list(R) == [3, 6]
+    assert np.allclose(X[:, 0], [2, 5])  # the features at the end of the decision restart
+    assert np.allclose(C, [[1.00, 1.01, 1.30], [1.20, 1.00, 1.05]])
+    _, y2, _, _ = stride_mod.label_rollouts(feats, costs, (0.25, 0.5, 1.0), tol=0.02)
+    assert np.allclose(np.exp(y2), [0.5, 0.5])
+    _, y3, _, _ = stride_mod.label_rollouts(feats, costs, (0.25, 0.5, 1.0), tol=0.06)
+    assert np.allclose(np.exp(y3), [0.5, 1.0])
+
+
 def test_stride_labels_pick_fastest_multiplier_per_bin():
     """Label rule: the multiplier that makes a slab of values final first wins the slab; a
     stride that defers corrections (small values accepted again later) pays for them."""
