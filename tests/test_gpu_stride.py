@@ -255,5 +255,5 @@ def test_trained_network_keeps_psi_and_beats_fixed_2h(fmm_lib):
     assert sl["restarts"] != sf["restarts"]  # the network did choose other strides
     # and not one stride for the whole solve: the multiplier follows the restart features
     _, st, rows = stride_mod.trace_solve(fmm_lib, F, p.h, p.sources, block=16, blob=blob)
-    used = {round(r["stride_used"] / p.h, 4) for r in rows[:-1]}  # the last is cut by the width
+    used = {round(r["stride_used"] / p.h, 4) for r in rows}  # width is infinite: none is cut
     assert len(used) > 1, used
