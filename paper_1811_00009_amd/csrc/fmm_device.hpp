@@ -137,10 +137,11 @@ struct Ctl {
     long long restarts;
     double final_bound;
     // batches with restarts of their own per problem (k_batched): the ready queue of
-    // problem tokens and the count of problems still running
+    // problem tokens, the count of problems still running and of phases started
     alignas(128) unsigned long long rq_head;
     alignas(128) unsigned long long rq_tail;
     alignas(128) int remaining;
+    unsigned long long progress;
     struct alignas(128) BarGroup {
         unsigned count;
     } bar_grp[kBarGroups];            // grid barrier arrivals, work-group w in group w % 64
@@ -151,6 +152,8 @@ struct Ctl {
 // phase << 40 | items << 20 | claims; phase 2 (r - 1) is the marching step of restart r,
 // phase 2 (r - 1) + 1 its exchanging step.  The list counters are the problem's own, by
 // restart parity, as the launch-wide ones of Ctl.
+constexpr int kItemsPerToken = 4;  // a phase of n items invites ceil(n / 4) work-groups
+
 struct alignas(128) SolveState {
     unsigned long long word;
     int done;         // items of the current phase finished

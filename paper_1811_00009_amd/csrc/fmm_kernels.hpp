@@ -932,8 +932,8 @@ __global__ void __launch_bounds__(64 * W)
 // per problem, so a push never finds it full.
 // Every wait in the queue ends: each pass that does not take a slot counts a poll, and every
 // 64 polls the work-group reads the abort flag and the watchdog.  The watchdog measures time
-// in which no token was put in anywhere in the launch; tokens are only put in when a phase
-// starts (at most kp.tokens per start), so once the phases stop the waits run out.
+// in which no phase of any problem started (Ctl::progress); phases are finite, so once they
+// stop the waits run out.
 template <typename R>
 __device__ __forceinline__ bool ring_wait_over(const KParams<R> &kp, int &polls, unsigned long long &seen,
                                                int64_t &t0)
@@ -941,9 +941,9 @@ __device__ __forceinline__ bool ring_wait_over(const KParams<R> &kp, int &polls,
     if ((++polls & 63) != 0) return false;
     Ctl *ctl = kp.ctl;
     if (read_abort(ctl)) return true;
-    const unsigned long long tl = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (tl != seen) {  // tokens are still being put in: progress
-        seen = tl;
+    const unsigned long long pr = __hip_atomic_load(&ctl->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (pr != seen) {  // phases are still starting: progress
+        seen = pr;
         t0 = wall_ticks();
         return false;
     }
@@ -959,7 +959,7 @@ __device__ void ring_push(const KParams<R> &kp, int q)
 {
     Ctl *ctl = kp.ctl;
     unsigned long long pos = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long seen = pos;
+    unsigned long long seen = __hip_atomic_load(&ctl->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int64_t t0 = wall_ticks();
     int polls = 0;
     for (;;) {
@@ -990,9 +990,9 @@ __device__ int ring_pop(const KParams<R> &kp)
     Ctl *ctl = kp.ctl;
     if (read_abort(ctl)) return -1;
     unsigned long long pos = __hip_atomic_load(&ctl->rq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long seen = __hip_atomic_load(&ctl->rq_tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long seen = __hip_atomic_load(&ctl->progress, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int64_t t0 = wall_ticks();
-    int polls = 0;
+    int polls = 0, nap = 1;
     for (;;) {
         unsigned long long *slot = kp.ring + (pos & kp.ring_mask);
         const unsigned long long v = __hip_atomic_load(slot, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1010,10 +1010,11 @@ __device__ int ring_pop(const KParams<R> &kp)
             }
             // pos now holds the current head
         } else {
-            if (dif < 0) {  // empty
+            if (dif < 0) {  // empty: poll less often the longer it stays empty (up to ~4k cycles)
                 if (__hip_atomic_load(&ctl->remaining, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <= 0)
                     return -1;
-                __builtin_amdgcn_s_sleep(2);
+                for (int k = 0; k < nap; ++k) __builtin_amdgcn_s_sleep(4);
+                nap = nap < 16 ? 2 * nap : 16;
             }
             pos = __hip_atomic_load(&ctl->rq_head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
@@ -1021,13 +1022,15 @@ __device__ int ring_pop(const KParams<R> &kp)
     }
 }
 
-// Problem q enters `phase` with n items: its claims and finished items start from zero and
-// the queue is topped up to min(n, kp.tokens) of its tokens, with at most that many pushes
-// (other work-groups may pop them as fast as they come, so the count alone would not end
-// the loop).  A token still queued from an earlier phase counts: whoever pops it later
-// claims from the new phase word, which is stored before the count is read.  So the phase
-// always has a token coming (n > 0), a problem never holds more than kp.tokens queue slots,
-// and a problem's tokens, hence the claims beyond n in one phase, stay bounded.  One thread.
+// Problem q enters `phase` with n items: its claims and finished items start from zero.
+// The work-group calling this (the one that finished the previous phase) goes on claiming
+// q's items itself, so the phase always has a worker; the queue is topped up with tokens
+// for ceil(n / kItemsPerToken) - 1 more work-groups (at most kp.tokens - 1), with at most
+// that many pushes (other work-groups may pop them as fast as they come, so the count
+// alone would not end the loop).  A token still queued from an earlier phase counts:
+// whoever pops it claims from the new phase word, which is stored before the count is
+// read.  A problem never holds more than kp.tokens queue slots, and its tokens, hence the
+// claims beyond n in one phase, stay bounded.  One thread.
 template <typename R>
 __device__ void batch_start(const KParams<R> &kp, int q, int64_t phase, int n)
 {
@@ -1035,7 +1038,9 @@ __device__ void batch_start(const KParams<R> &kp, int q, int64_t phase, int n)
     st.done = 0;  // ordered before the phase word by the release below
     __hip_atomic_store(&st.word, ((unsigned long long)phase << 40) | ((unsigned long long)n << 20),
                        __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const int want = n < kp.tokens ? n : kp.tokens;
+    __hip_atomic_fetch_add(&kp.ctl->progress, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int helpers = (n + kItemsPerToken - 1) / kItemsPerToken - 1;
+    const int want = helpers < kp.tokens - 1 ? helpers : kp.tokens - 1;
     for (int k = 0; k < want; ++k) {
         const int had = __hip_atomic_fetch_add(&st.queued, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (had >= want) {
