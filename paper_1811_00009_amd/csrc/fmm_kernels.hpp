@@ -1094,14 +1094,21 @@ __global__ void __launch_bounds__(64 * W)
     const int tid = threadIdx.x;
     Ctl *ctl = kp.ctl;
     SolveState *S = kp.solves;
-    __shared__ int s_q;
+    __shared__ int s_q, s_keep, s_stop;
     __shared__ unsigned long long s_w;
     __shared__ unsigned long long s_feat[9];  // no restart features in batches
     if (tid < 9) s_feat[tid] = 0ull;
     Totals tot;
     FMM_CYC_DECL;
-    if (read_abort(ctl)) return;
-    int q = -1;
+    int q = -1;  // (ring_pop, thread 0's first step, reads the abort flag)
+    // Memory ordering once per phase, not per item (thread 0's state): the acquire when this
+    // work-group first claims an item of a phase (what it reads was written in earlier
+    // phases, by any work-group on any XCD), and the release when the phase has no item
+    // left for it, before its finished items are counted (pend of them, of a phase of
+    // pend_n items).  The phase cannot end before that count, and this work-group makes it
+    // at its very next claim, so nothing waits on the delay.
+    int cur_q = -1, pend = 0, pend_n = 0;
+    int64_t cur_phase = -1, pend_phase = -1;
     for (;;) {
         if (q < 0) {
             if (tid == 0) s_q = ring_pop<R>(kp);
@@ -1114,17 +1121,48 @@ __global__ void __launch_bounds__(64 * W)
                 break;
             }
         }
+        // thread 0 decides for the work-group (the abort flag read once, so every wave
+        // takes the same branch)
+        if (tid == 0) s_stop = read_abort(ctl);
+        __syncthreads();
+        if (s_stop) break;
         if (tid == 0) {
-            s_w = __hip_atomic_fetch_add(&S[q].word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the phase's lists and counters
+            const unsigned long long w0 =
+                __hip_atomic_fetch_add(&S[q].word, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int64_t ph = (int64_t)(w0 >> 40);
+            const int nn = (int)((w0 >> 20) & 0xFFFFFu), ii = (int)(w0 & 0xFFFFFu);
+            int keep = 1;
+            if (ii >= nn) {
+                // no item left for this work-group: count the ones it finished; the
+                // work-group that completes the phase moves q on and keeps working on it
+                keep = 0;
+                if (pend > 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    const int d = __hip_atomic_fetch_add(&S[q].done, pend, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if (d + pend == pend_n) {
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        batch_advance<R>(kp, q, pend_phase);
+                        keep = 1;
+                    }
+                    pend = 0;
+                }
+            } else if (q != cur_q || ph != cur_phase) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the phase's lists and tiles
+                cur_q = q;
+                cur_phase = ph;
+            }
+            s_w = w0;
+            s_keep = keep;
         }
         __syncthreads();
         const unsigned long long wv = s_w;
+        const int keep = s_keep;
         __syncthreads();
         const int64_t phase = (int64_t)(wv >> 40);
         const int n = (int)((wv >> 20) & 0xFFFFFu), i = (int)(wv & 0xFFFFFu);
-        if (i >= n) {  // the phase has no item left: drop the token
-            q = -1;
+        if (i >= n) {  // drained: drop the token unless this work-group moved q on
+            if (!keep) q = -1;
             continue;
         }
         const ProbDesc pd = kp.prob[q];
@@ -1183,17 +1221,14 @@ __global__ void __launch_bounds__(64 * W)
             if (tid == 0) raise_error(ctl, kErrList);
             break;
         }
-        // the item is done; the work-group finishing the phase's last item moves q on
+        // the item is done (every lane's writes are complete: both steps end with a
+        // barrier); it is counted, with the release, when the phase runs dry for this
+        // work-group
         if (tid == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            const int d = __hip_atomic_fetch_add(&S[q].done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (d == n - 1) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                batch_advance<R>(kp, q, phase);
-            }
+            ++pend;
+            pend_n = n;
+            pend_phase = phase;
         }
-        __syncthreads();
-        if (read_abort(ctl)) break;
     }
     if (tid == 0) flush_totals(ctl, tot);
 }
