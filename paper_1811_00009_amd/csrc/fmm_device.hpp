@@ -41,7 +41,7 @@ __device__ __forceinline__ bool is_known(uint32_t t) { return t >= kKnownFix; } 
 // overlaps, so the segments add up to more than a pop costs without them; both totals
 // are reported.  In the normal build every mark compiles to nothing.
 #ifdef FMM_CYCLES
-constexpr int kCycSegs = 16;
+constexpr int kCycSegs = 18;
 constexpr int kCycRows = 8192;
 __device__ unsigned long long fmm_cyc_rows[kCycRows][kCycSegs];
 struct Cyc {
@@ -567,6 +567,135 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
     mk = __builtin_amdgcn_readfirstlane(mk);
     FMM_CYC(2);
     return MinPick<R>{KeyBits<R>::from(h, l), (int)(mk >> 16), (int)(mk & 0xffffu)};
+}
+
+// The two smallest (psi, key) entries of a band of at most 1024 slots, all in LDS, marched
+// by one wave (the two-point step of march_block).  Each lane takes the minimum of its
+// slots and, with that slot left out, the next one (two shallow trees each, as in
+// band_chunk_min); the cross-lane step runs once on the lanes' minima and once more with
+// the winning lane offering its second.  Slots per lane as in band_argmin: 1, 2 or 4 for
+// bands of at most 256 slots, else 8 per 512-slot chunk.
+template <typename R, int S>
+__device__ __forceinline__ void lane_top2(const R (&vs)[S], const uint32_t (&ks)[S], R &v1, uint32_t &k1,
+                                          R &v2, uint32_t &k2)
+{
+    const R inf = (R)INFINITY;
+    R m = vs[0];
+#pragma unroll
+    for (int j = 1; j < S; ++j) m = val_min(m, vs[j]);
+    uint32_t km = ~0u;
+#pragma unroll
+    for (int j = 0; j < S; ++j) km = min(km, val_eq(vs[j], m) ? ks[j] : ~0u);
+    R w[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) w[j] = ks[j] == km ? inf : vs[j];
+    R m2 = w[0];
+#pragma unroll
+    for (int j = 1; j < S; ++j) m2 = val_min(m2, w[j]);
+    uint32_t k2m = ~0u;
+#pragma unroll
+    for (int j = 0; j < S; ++j) k2m = min(k2m, (val_eq(w[j], m2) && ks[j] != km) ? ks[j] : ~0u);
+    v1 = m;
+    k1 = km;
+    v2 = m2;
+    k2 = k2m;
+}
+
+template <typename R>
+__device__ __forceinline__ bool key_less(R va, uint32_t ka, R vb, uint32_t kb)
+{
+    return (va < vb) | (val_eq(va, vb) & (ka < kb));
+}
+
+// Merge the top-2 (b1 <= b2) of one group of slots into the running top-2 (a1 <= a2).
+template <typename R>
+__device__ __forceinline__ void top2_merge(R &av1, uint32_t &ak1, R &av2, uint32_t &ak2, R bv1, uint32_t bk1,
+                                           R bv2, uint32_t bk2)
+{
+    const bool bfirst = key_less(bv1, bk1, av1, ak1);
+    // the overall first, and the best of the remaining three candidates for second
+    const R fv = bfirst ? bv1 : av1;
+    const uint32_t fk = bfirst ? bk1 : ak1;
+    const R cv = bfirst ? av1 : bv1;  // the other list's first
+    const uint32_t ck = bfirst ? ak1 : bk1;
+    const R dv = bfirst ? bv2 : av2;  // the winning list's second
+    const uint32_t dk = bfirst ? bk2 : ak2;
+    const bool csec = key_less(cv, ck, dv, dk);
+    av1 = fv;
+    ak1 = fk;
+    av2 = csec ? cv : dv;
+    ak2 = csec ? ck : dk;
+}
+
+template <typename R, int S, typename PsiP>
+__device__ __forceinline__ void lane_slots_top2(const FMM_LDS uint16_t *s_band, PsiP s_psi, int n, int base,
+                                                R &v1, uint32_t &k1, R &v2, uint32_t &k2)
+{
+    uint32_t w[(S + 1) / 2];
+    if constexpr (S == 8) {
+        const v4u r = *reinterpret_cast<const FMM_LDS v4u *>(s_band + base);
+        w[0] = r.x;
+        w[1] = r.y;
+        w[2] = r.z;
+        w[3] = r.w;
+    } else if constexpr (S == 4) {
+        typedef unsigned int v2u __attribute__((ext_vector_type(2)));
+        const v2u r = *reinterpret_cast<const FMM_LDS v2u *>(s_band + base);
+        w[0] = r.x;
+        w[1] = r.y;
+    } else if constexpr (S == 2) {
+        w[0] = *reinterpret_cast<const FMM_LDS uint32_t *>(s_band + base);
+    } else {
+        w[0] = s_band[base];
+    }
+    uint32_t ids[S], ks[S];
+    R vs[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const uint32_t id = (w[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
+        ids[j] = (uint32_t)(base + j) < (uint32_t)n ? id : 0u;  // tile point 0: +inf
+        ks[j] = (ids[j] << 16) | (uint32_t)(base + j);
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) vs[j] = s_psi[ids[j]];
+    lane_top2<R, S>(vs, ks, v1, k1, v2, k2);
+}
+
+template <typename R, typename PsiP>
+__device__ __forceinline__ void band_top2(const FMM_LDS uint16_t *s_band, PsiP s_psi, int n,
+                                          MinPick<R> &a, MinPick<R> &b FMM_CYC_PARAM)
+{
+    const int lane = threadIdx.x & 63;
+    R v1, v2;
+    uint32_t k1, k2;
+    if (n <= 64) lane_slots_top2<R, 1, PsiP>(s_band, s_psi, n, lane, v1, k1, v2, k2);
+    else if (n <= 128) lane_slots_top2<R, 2, PsiP>(s_band, s_psi, n, 2 * lane, v1, k1, v2, k2);
+    else if (n <= 256) lane_slots_top2<R, 4, PsiP>(s_band, s_psi, n, 4 * lane, v1, k1, v2, k2);
+    else {
+        lane_slots_top2<R, 8, PsiP>(s_band, s_psi, n, 8 * lane, v1, k1, v2, k2);
+        if (n > 512) {
+            R u1, u2;
+            uint32_t l1, l2;
+            lane_slots_top2<R, 8, PsiP>(s_band, s_psi, n, 512 + 8 * lane, u1, l1, u2, l2);
+            top2_merge<R>(v1, k1, v2, k2, u1, l1, u2, l2);
+        }
+    }
+    FMM_CYC(1);
+    uint32_t mh, ml, mk;
+    wave_pick<R>(v1, k1, mh, ml, mk);
+    mh = __builtin_amdgcn_readfirstlane(mh);
+    ml = __builtin_amdgcn_readfirstlane(ml);
+    mk = __builtin_amdgcn_readfirstlane(mk);
+    a = MinPick<R>{KeyBits<R>::from(mh, ml), (int)(mk >> 16), (int)(mk & 0xffffu)};
+    // the second: the winning lane offers its next entry, every other lane its first
+    const bool own = k1 == mk;
+    uint32_t nh, nl, nk;
+    wave_pick<R>(own ? v2 : v1, own ? k2 : k1, nh, nl, nk);
+    nh = __builtin_amdgcn_readfirstlane(nh);
+    nl = __builtin_amdgcn_readfirstlane(nl);
+    nk = __builtin_amdgcn_readfirstlane(nk);
+    b = MinPick<R>{KeyBits<R>::from(nh, nl), (int)(nk >> 16), (int)(nk & 0xffffu)};
+    FMM_CYC(2);
 }
 
 // ---------------------------------------------------------------- Solve_Quadratic (Alg. 3)

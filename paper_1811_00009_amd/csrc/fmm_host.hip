@@ -1318,7 +1318,7 @@ int fmm_cycle_account(unsigned long long *out, int reset)
     unsigned long long h[4];
     HIPCHK(hipMemcpy(h, clk, sizeof(h), hipMemcpyDeviceToHost));
     (void)hipFree(clk);
-    out[16] = (unsigned long long)((double)(h[1] - h[0]) / (double)(h[3] - h[2]) * 1e8);
+    out[kCycSegs] = (unsigned long long)((double)(h[1] - h[0]) / (double)(h[3] - h[2]) * 1e8);
     if (reset) {
         std::memset(rows, 0, sizeof(rows));
         HIPCHK(hipMemcpyToSymbol(HIP_SYMBOL(fmm_cyc_rows), rows, sizeof(rows)));

@@ -218,6 +218,13 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     const int g = lane >> 2, kk = lane & 3;
     const int dI = (g == 1) - (g == 0), dJ = (g == 3) - (g == 2), dK = (g == 5) - (g == 4);
     const int dOff = dI + P * (dJ + P * dK);
+    // Two accepted points per step (one wave, tile and band in LDS): quads 6-11 take the
+    // face neighbours of the second point the way quads 0-5 take the first's
+    constexpr bool PAIR = TL && W == 1;
+    const int gdir = g < 6 ? g : (g < 12 ? g - 6 : 0);
+    const int gpt = g < 6 ? 0 : (g < 12 ? 1 : 2);
+    const int eI = (gdir == 1) - (gdir == 0), eJ = (gdir == 3) - (gdir == 2), eK = (gdir == 5) - (gdir == 4);
+    const int eOff = eI + P * (eJ + P * eK);
     uint32_t mine = 0;  // faces of Upsilon, recorded as points are lowered (tile in memory)
     constexpr int kMid = (B / 2) * (1 + P + P * P);  // an interior point of the tile
     bool active = true;
@@ -231,6 +238,183 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             active = false;
             exit_min = inf;
             break;
+        }
+        if constexpr (PAIR) {
+            if (n <= cap) {
+                // Two steps of Alg. 4 at once.  p1 is the band's minimum; p2, the next entry,
+                // is taken with it when it lies at Manhattan distance >= 4 from p1: then p1's
+                // step (p1 and its face neighbours written, their neighbours read) and p2's
+                // touch disjoint points.  p2 is the point the sequential march accepts next
+                // unless p1's step lowers a point below it, which is checked once the roots
+                // are in: only then are p2's values, tag and slot written.  Every step is
+                // the one of the sequential order, so psi and the counts are unchanged.
+                MinPick<R> m1, m2;
+                band_top2<R>(s_band, s_psi, n, m1, m2 FMM_CYC_ARG);
+                if (m1.v > rbound) {  // beyond the restart bound: stop (deactivate past width)
+                    if ((double)m1.v > pd.width) active = false;
+                    exit_min = m1.v;
+                    break;
+                }
+                const int p1 = m1.idx;
+                FMM_CYC_COUNT(14, n <= 64 ? 1 : 0);
+                FMM_CYC_COUNT(15, n <= 256 ? 1 : 0);
+                if (++npops > pop_cap) {
+                    raise_error(kp.ctl, kErrPopCap);
+                    exit_min = m1.v;
+                    break;
+                }
+                int p2 = p1;
+                bool pair = false;
+                if (n >= 2 && !(m2.v > rbound) && npops < pop_cap) {
+                    const int b2 = m2.idx;
+                    const int di = p1 % P - b2 % P, dj = (p1 / P) % P - (b2 / P) % P,
+                              dk = p1 / (P * P) - b2 / (P * P);
+                    pair = (di < 0 ? -di : di) + (dj < 0 ? -dj : dj) + (dk < 0 ? -dk : dk) >= 4;
+                    if (pair) p2 = b2;
+                }
+                const int pp = gpt == 1 ? p2 : p1;
+                const R vpp = gpt == 1 ? m2.v : m1.v;
+                R rhs_mem = (R)0;
+                if constexpr (!Gm::RHS_LDS) {
+                    const int ql = pp + eOff;
+                    rhs_mem = g_rhs[ql < 0 ? 0 : (ql > T - 1 ? T - 1 : ql)];
+                }
+                const uint32_t up = (uint32_t)pp;
+                const int pi = (int)(up % P), pj = (int)((up / P) % P), pk = (int)(up / (P * P));
+                const int qi = pi + eI, qj = pj + eJ, qk = pk + eK;
+                const bool inb = (gpt == 0 || (gpt == 1 && pair)) && kk < 3 &&
+                                 (unsigned)(qi - 1) < (unsigned)B && (unsigned)(qj - 1) < (unsigned)B &&
+                                 (unsigned)(qk - 1) < (unsigned)B;
+                // lane 48 reads p1's own tag, lane 49 p2's
+                const int q = inb ? pp + eOff : (lane == 49 ? p2 : p1);
+                R rhs = (R)0;
+                if (inb) {
+                    if constexpr (Gm::RHS_LDS) rhs = s_rhs[q];
+                    else rhs = rhs_mem;
+                }
+                const uint8_t tq = s_tag[q];
+                const R psq = s_psi[q];
+                R lo[3], hi[3];
+                uint32_t tlo[3], thi[3];
+                if constexpr (Gm::RHS_LDS) {
+                    const int qs = inb ? q : kMid;
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+                        lo[ax] = s_psi[qs - off];
+                        hi[ax] = s_psi[qs + off];
+                        tlo[ax] = s_tag[qs - off];
+                        thi[ax] = s_tag[qs + off];
+                    }
+                }
+                // the band's last two slots, for Remove_Min of one or both points
+                const int last1 = __builtin_amdgcn_readfirstlane((int)s_band[n - 1]);
+                const int last2 = n >= 2 ? __builtin_amdgcn_readfirstlane((int)s_band[n - 2]) : 0;
+                FMM_CYC(3);
+                const bool solve = inb && (tq & kStatus) != kKnownFix && psq > vpp;
+                R t = inf, r1 = inf, r2 = inf;
+                if (solve) {
+                    FMM_CYC_LSTART();
+                    R c[3];
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax) {
+                        // the accepted point is q's low neighbour for the + directions and its
+                        // high neighbour for the - directions, on the quad's own axis; its tag
+                        // is written after the check below, so it is taken as known here
+                        const bool own = ax == (gdir >> 1);
+                        bool klo, khi;
+                        if constexpr (Gm::RHS_LDS) {
+                            klo = is_known(tlo[ax]) || (own && (gdir & 1));
+                            khi = is_known(thi[ax]) || (own && !(gdir & 1));
+                        } else {
+                            const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+                            lo[ax] = s_psi[q - off];
+                            hi[ax] = s_psi[q + off];
+                            klo = is_known(s_tag[q - off]) || (own && (gdir & 1));
+                            khi = is_known(s_tag[q + off]) || (own && !(gdir & 1));
+                        }
+                        c[ax] = axis_candidate<R>(psq, lo[ax], klo, hi[ax], khi);
+                    }
+                    FMM_CYC_L(8);
+                    FMM_CYC_LFULL(9);
+                    t = quad_root_k<R>(c[0], c[1], c[2], rhs, kk, r1, r2);
+                    FMM_CYC_L(10);
+                    FMM_CYC_COUNT(11, 1);
+                }
+                const R t2 = quad_bcast<1>(t), t3 = quad_bcast<2>(t);
+                bool low = false, ins = false;
+                R tf = inf;
+                if (solve && kk == 0) {
+                    tf = t;
+                    if (r1 < inf && tf > r1) {
+                        tf = t2;
+                        if (r2 < inf && tf > r2) tf = t3;
+                    }
+                    if (tf < psq) {
+                        low = true;
+                        ins = !(tq & kInBand);
+                    }
+                }
+                // p2 is the next point unless p1's step lowered a point below it
+                const uint64_t beat = ballot(low && gpt == 0 && key_less<R>(tf, (uint32_t)q, m2.v, (uint32_t)p2));
+                const bool acc2 = pair && beat == 0;
+                const bool wr = low && (gpt == 0 || acc2);
+                if (wr) {
+                    s_psi[q] = tf;
+                    s_tag[q] = kBand | kInBand;
+                }
+                // KNOWN_NEW unless KNOWN_FIX; the points leave the band
+                if (lane == 48 || (lane == 49 && acc2))
+                    s_tag[q] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
+                FMM_CYC(4);
+                FMM_CYC_COUNT(12, acc2 ? 2 : 1);
+                FMM_CYC_COUNT(16, 1);  // two-point steps taken, and how many accepted p2
+                FMM_CYC_COUNT(17, acc2 ? 1 : 0);
+                if (!acc2) {  // Remove_Min of p1: the last slot moves into its hole
+                    if (lane == 50 && m1.slot != n - 1) s_band[m1.slot] = (uint16_t)last1;
+                    n -= 1;
+                } else {
+                    // Remove_Min of both: the holes below n - 2 take the entries of the last
+                    // two slots that are not holes themselves (as many of each)
+                    const int s1 = m1.slot, s2 = m2.slot, e1 = n - 1, e2 = n - 2;
+                    int h0 = -1, h1 = -1, f0 = 0, f1 = 0;
+                    if (s1 < e2) h0 = s1;
+                    if (s2 < e2) {
+                        if (h0 < 0) h0 = s2;
+                        else h1 = s2;
+                    }
+                    bool have0 = false;
+                    if (e2 != s1 && e2 != s2) {
+                        f0 = last2;
+                        have0 = true;
+                    }
+                    if (e1 != s1 && e1 != s2) {
+                        if (!have0) f0 = last1;
+                        else f1 = last1;
+                    }
+                    if (lane == 50 && h0 >= 0) s_band[h0] = (uint16_t)f0;
+                    if (lane == 51 && h1 >= 0) s_band[h1] = (uint16_t)f1;
+                    n -= 2;
+                    ++npops;
+                }
+                const uint64_t bal = ballot(ins && wr);
+                if (ins && wr) {
+                    const int at = n + (int)lanes_below(bal);
+                    if (at < cap) s_band[at] = (uint16_t)q;
+                    else __builtin_nontemporal_store((uint16_t)q, g_band + at);
+                }
+                n += (int)__popcll(bal);
+                if (n + 8 > cap) {
+                    // the band reaches its memory part: make this wave's stores there visible
+                    // to its own later loads
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                FMM_CYC(5);
+                continue;
+            }
         }
         const MinPick<R> mp = band_argmin<R, W>(s_band, g_band, cap, s_psi, n FMM_CYC_ARG);
         if (mp.v > rbound) {  // beyond the restart bound: stop (deactivate past width)

@@ -48,7 +48,7 @@ def main():
     lib = fmm.load()
     lib.fmm_cycle_account.argtypes = [C.POINTER(C.c_ulonglong), C.c_int]
     lib.fmm_cycle_account.restype = C.c_int
-    acc = (C.c_ulonglong * 17)()
+    acc = (C.c_ulonglong * 19)()
 
     p = inputs.coarse_cells(args.n, 64, seed=(3,), materialize=False)
     F = inputs.expand_cells_device(p.meta["V"], args.n, torch)
@@ -60,7 +60,7 @@ def main():
     torch.cuda.synchronize()
     assert lib.fmm_cycle_account(acc, 0) == 0
     a = list(acc)
-    hz = a[16]
+    hz = a[18]
     pops, marches, solves0 = a[12], a[13], a[11]
     print(f"[cycles] loop {st['loop_ms']:.1f} ms, {st['pops']} pops, {st['restarts']} restarts; "
           f"account: {pops} pops, {marches} marches, clock {hz / 1e9:.3f} GHz",
@@ -91,6 +91,9 @@ def main():
     lines.append(f"Band size at the pick: {small / max(pops, 1) * 100:.1f} % of pops at most 64 slots, "
                  f"{mid / max(pops, 1) * 100:.1f} % 65-256, "
                  f"{(pops - a[15]) / max(pops, 1) * 100:.1f} % more than 256.")
+    lines.append(f"Steps of the two-point march (band in LDS): {a[16]:,}, of which {a[17]:,} accepted two "
+                 f"points; {pops:,} pops in {pops - a[17]:,} steps "
+                 f"({(pops - a[17]) / max(pops, 1) * 100:.1f} % of the pops).")
     inst_pop_s = (sum(a[k] for k in range(8))) / hz / max(pops, 1)
     lines.append("")
     lines.append(f"Run: {st['pops']} pops, {marches} marches, {st['restarts']} restarts, loop "
