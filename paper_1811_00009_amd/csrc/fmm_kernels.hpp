@@ -307,9 +307,11 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                         thi[ax] = s_tag[qs + off];
                     }
                 }
-                // the band's last two slots, for Remove_Min of one or both points
-                const int last1 = __builtin_amdgcn_readfirstlane((int)s_band[n - 1]);
-                const int last2 = n >= 2 ? __builtin_amdgcn_readfirstlane((int)s_band[n - 2]) : 0;
+                // the band's last two slots, for Remove_Min of one or both points (read by
+                // every lane, used by the writing lanes at the end of the step, so that no
+                // wait for them falls before the solves)
+                const uint16_t last1 = s_band[n - 1];
+                const uint16_t last2 = s_band[n >= 2 ? n - 2 : n - 1];
                 FMM_CYC(3);
                 const bool solve = inb && (tq & kStatus) != kKnownFix && psq > vpp;
                 R t = inf, r1 = inf, r2 = inf;
@@ -357,6 +359,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 }
                 // p2 is the next point unless p1's step lowered a point below it
                 const uint64_t beat = ballot(low && gpt == 0 && key_less<R>(tf, (uint32_t)q, m2.v, (uint32_t)p2));
+                const uint64_t ins1 = ballot(ins && gpt == 0), ins2 = ballot(ins && gpt == 1);
                 const bool acc2 = pair && beat == 0;
                 const bool wr = low && (gpt == 0 || acc2);
                 if (wr) {
@@ -377,27 +380,20 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     // Remove_Min of both: the holes below n - 2 take the entries of the last
                     // two slots that are not holes themselves (as many of each)
                     const int s1 = m1.slot, s2 = m2.slot, e1 = n - 1, e2 = n - 2;
-                    int h0 = -1, h1 = -1, f0 = 0, f1 = 0;
+                    int h0 = -1, h1 = -1;
                     if (s1 < e2) h0 = s1;
                     if (s2 < e2) {
                         if (h0 < 0) h0 = s2;
                         else h1 = s2;
                     }
-                    bool have0 = false;
-                    if (e2 != s1 && e2 != s2) {
-                        f0 = last2;
-                        have0 = true;
-                    }
-                    if (e1 != s1 && e1 != s2) {
-                        if (!have0) f0 = last1;
-                        else f1 = last1;
-                    }
-                    if (lane == 50 && h0 >= 0) s_band[h0] = (uint16_t)f0;
-                    if (lane == 51 && h1 >= 0) s_band[h1] = (uint16_t)f1;
+                    // the fillers in order: slot e2's entry if it is not a hole, then e1's
+                    const bool e2_stays = e2 != s1 && e2 != s2;
+                    if (lane == 50 && h0 >= 0) s_band[h0] = e2_stays ? last2 : last1;
+                    if (lane == 51 && h1 >= 0) s_band[h1] = last1;  // both fillers: e2's, e1's
                     n -= 2;
                     ++npops;
                 }
-                const uint64_t bal = ballot(ins && wr);
+                const uint64_t bal = ins1 | (acc2 ? ins2 : 0ull);
                 if (ins && wr) {
                     const int at = n + (int)lanes_below(bal);
                     if (at < cap) s_band[at] = (uint16_t)q;

@@ -17,9 +17,11 @@ from typing import Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 # FMM_SANITIZE=1: the build with the host code under AddressSanitizer and UBSan
-# (build.py --sanitize; CPU tests with libasan preloaded)
-LIB_PATH = os.path.join(_HERE, "libfmm_hip_san.so" if os.environ.get("FMM_SANITIZE") == "1"
-                        else "libfmm_hip.so")
+# (build.py --sanitize; CPU tests with libasan preloaded); FMM_LIB=<file>: another build of
+# the library in this directory (variants timed side by side)
+LIB_PATH = os.path.join(_HERE, os.path.basename(os.environ["FMM_LIB"]) if os.environ.get("FMM_LIB")
+                        else ("libfmm_hip_san.so" if os.environ.get("FMM_SANITIZE") == "1"
+                              else "libfmm_hip.so"))
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EHIP, FMM_ENOCONV, FMM_ENOTSUP = 0, -1, -2, -3, -4, -5
 FMM_F32, FMM_F64 = 0, 1
