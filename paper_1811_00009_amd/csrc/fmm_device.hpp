@@ -601,6 +601,32 @@ __device__ __forceinline__ void lane_top2(const R (&vs)[S], const uint32_t (&ks)
     k2 = k2m;
 }
 
+// Whether tile points a and b (indices i + P j + P^2 k) lie at Manhattan distance >= 4, the
+// condition for taking two points in one march step.  For P >= 8 it is decided from the
+// index difference d = b - a alone: a pair closer than 4 has d = di + P dj + P^2 dk with
+// |di| + |dj| + |dk| <= 3, and the decomposition below (offsets that keep every step
+// non-negative for such d) recovers exactly those (di, dj, dk), so every close pair is
+// found.  A distant pair whose difference decomposes to a short one is declined as well
+// (0.09 % of the distant pairs at P = 18), which costs one one-point step and no
+// correctness.  Smaller tiles use the coordinates themselves.
+template <int P>
+__device__ __forceinline__ bool far_apart(int a, int b)
+{
+    if constexpr (P >= 8) {
+        const int d = b - a;
+        const uint32_t e = (uint32_t)(d + 3 * P * P + P * P / 2);
+        const uint32_t qk = e / (uint32_t)(P * P);
+        const uint32_t g = e - qk * (uint32_t)(P * P) - (uint32_t)(P * P / 2) + (uint32_t)(P / 2 + 3 * P);
+        const uint32_t qj = g / (uint32_t)P;
+        const int di = (int)(g - qj * (uint32_t)P) - P / 2, dj = (int)qj - 3, dk = (int)qk - 3;
+        const int m = (di < 0 ? -di : di) + (dj < 0 ? -dj : dj) + (dk < 0 ? -dk : dk);
+        return (d > 3 * P * P) | (d < -3 * P * P) | (m > 3);
+    } else {
+        const int di = a % P - b % P, dj = (a / P) % P - (b / P) % P, dk = a / (P * P) - b / (P * P);
+        return (di < 0 ? -di : di) + (dj < 0 ? -dj : dj) + (dk < 0 ? -dk : dk) >= 4;
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ bool key_less(R va, uint32_t ka, R vb, uint32_t kb)
 {

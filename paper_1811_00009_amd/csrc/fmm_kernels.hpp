@@ -225,6 +225,17 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
     const int gpt = g < 6 ? 0 : (g < 12 ? 1 : 2);
     const int eI = (gdir == 1) - (gdir == 0), eJ = (gdir == 3) - (gdir == 2), eK = (gdir == 5) - (gdir == 4);
     const int eOff = eI + P * (eJ + P * eK);
+    // The accepted point is q's low neighbour for the + directions and its high neighbour
+    // for the - directions, on the quad's own axis; its tag is written after the step's
+    // check, so it is taken as known: these tag bits (a KNOWN status) are or-ed into the
+    // tag read on that side.  Kept as register data, not lane masks.
+    uint32_t flo[3], fhi[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const bool own = ax == (gdir >> 1);
+        flo[ax] = (own && (gdir & 1)) ? kKnownFix : 0u;
+        fhi[ax] = (own && !(gdir & 1)) ? kKnownFix : 0u;
+    }
     uint32_t mine = 0;  // faces of Upsilon, recorded as points are lowered (tile in memory)
     constexpr int kMid = (B / 2) * (1 + P + P * P);  // an interior point of the tile
     bool active = true;
@@ -242,7 +253,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         if constexpr (PAIR) {
             if (n <= cap) {
                 // Two steps of Alg. 4 at once.  p1 is the band's minimum; p2, the next entry,
-                // is taken with it when it lies at Manhattan distance >= 4 from p1: then p1's
+                // is taken with it only when it lies at Manhattan distance >= 4 from p1
+                // (far_apart, which may decline a few such pairs as well): then p1's
                 // step (p1 and its face neighbours written, their neighbours read) and p2's
                 // touch disjoint points.  p2 is the point the sequential march accepts next
                 // unless p1's step lowers a point below it, which is checked once the roots
@@ -266,14 +278,17 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 int p2 = p1;
                 bool pair = false;
                 if (n >= 2 && !(m2.v > rbound) && npops < pop_cap) {
-                    const int b2 = m2.idx;
-                    const int di = p1 % P - b2 % P, dj = (p1 / P) % P - (b2 / P) % P,
-                              dk = p1 / (P * P) - b2 / (P * P);
-                    pair = (di < 0 ? -di : di) + (dj < 0 ? -dj : dj) + (dk < 0 ? -dk : dk) >= 4;
-                    if (pair) p2 = b2;
+                    pair = far_apart<P>(p1, m2.idx);
+                    if (pair) p2 = m2.idx;
                 }
-                const int pp = gpt == 1 ? p2 : p1;
-                const R vpp = gpt == 1 ? m2.v : m1.v;
+                // the lane's quad group, kk and lane id, re-read in each step: the lane
+                // tests below are then computed where they are used instead of being held
+                // across the loop as 64-bit lane masks (which the scalar registers cannot
+                // hold alongside the loop's state)
+                int gpt_s = gpt, kk_s = kk, ln_s = lane;
+                asm volatile("" : "+v"(gpt_s), "+v"(kk_s), "+v"(ln_s));
+                const int pp = gpt_s == 1 ? p2 : p1;
+                const R vpp = gpt_s == 1 ? m2.v : m1.v;
                 R rhs_mem = (R)0;
                 if constexpr (!Gm::RHS_LDS) {
                     const int ql = pp + eOff;
@@ -282,11 +297,11 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 const uint32_t up = (uint32_t)pp;
                 const int pi = (int)(up % P), pj = (int)((up / P) % P), pk = (int)(up / (P * P));
                 const int qi = pi + eI, qj = pj + eJ, qk = pk + eK;
-                const bool inb = (gpt == 0 || (gpt == 1 && pair)) && kk < 3 &&
+                const bool inb = (gpt_s == 0 || (gpt_s == 1 && pair)) && kk_s < 3 &&
                                  (unsigned)(qi - 1) < (unsigned)B && (unsigned)(qj - 1) < (unsigned)B &&
                                  (unsigned)(qk - 1) < (unsigned)B;
                 // lane 48 reads p1's own tag, lane 49 p2's
-                const int q = inb ? pp + eOff : (lane == 49 ? p2 : p1);
+                const int q = inb ? pp + eOff : (ln_s == 49 ? p2 : p1);
                 R rhs = (R)0;
                 if (inb) {
                     if constexpr (Gm::RHS_LDS) rhs = s_rhs[q];
@@ -294,9 +309,11 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 }
                 const uint8_t tq = s_tag[q];
                 const R psq = s_psi[q];
+                // the stencil is read in the same LDS round trip as q's own tag and value,
+                // for every block size: one wait before the solves instead of two
                 R lo[3], hi[3];
                 uint32_t tlo[3], thi[3];
-                if constexpr (Gm::RHS_LDS) {
+                {
                     const int qs = inb ? q : kMid;
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
@@ -320,33 +337,21 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     R c[3];
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
-                        // the accepted point is q's low neighbour for the + directions and its
-                        // high neighbour for the - directions, on the quad's own axis; its tag
-                        // is written after the check below, so it is taken as known here
-                        const bool own = ax == (gdir >> 1);
-                        bool klo, khi;
-                        if constexpr (Gm::RHS_LDS) {
-                            klo = is_known(tlo[ax]) || (own && (gdir & 1));
-                            khi = is_known(thi[ax]) || (own && !(gdir & 1));
-                        } else {
-                            const int off = ax == 0 ? 1 : (ax == 1 ? P : P * P);
-                            lo[ax] = s_psi[q - off];
-                            hi[ax] = s_psi[q + off];
-                            klo = is_known(s_tag[q - off]) || (own && (gdir & 1));
-                            khi = is_known(s_tag[q + off]) || (own && !(gdir & 1));
-                        }
+                        // the accepted point reads as known (flo, fhi)
+                        const bool klo = is_known(tlo[ax] | flo[ax]);
+                        const bool khi = is_known(thi[ax] | fhi[ax]);
                         c[ax] = axis_candidate<R>(psq, lo[ax], klo, hi[ax], khi);
                     }
                     FMM_CYC_L(8);
                     FMM_CYC_LFULL(9);
-                    t = quad_root_k<R>(c[0], c[1], c[2], rhs, kk, r1, r2);
+                    t = quad_root_k<R>(c[0], c[1], c[2], rhs, kk_s, r1, r2);
                     FMM_CYC_L(10);
                     FMM_CYC_COUNT(11, 1);
                 }
                 const R t2 = quad_bcast<1>(t), t3 = quad_bcast<2>(t);
                 bool low = false, ins = false;
                 R tf = inf;
-                if (solve && kk == 0) {
+                if (solve && kk_s == 0) {
                     tf = t;
                     if (r1 < inf && tf > r1) {
                         tf = t2;
@@ -358,23 +363,23 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     }
                 }
                 // p2 is the next point unless p1's step lowered a point below it
-                const uint64_t beat = ballot(low && gpt == 0 && key_less<R>(tf, (uint32_t)q, m2.v, (uint32_t)p2));
-                const uint64_t ins1 = ballot(ins && gpt == 0), ins2 = ballot(ins && gpt == 1);
+                const uint64_t beat = ballot(low && gpt_s == 0 && key_less<R>(tf, (uint32_t)q, m2.v, (uint32_t)p2));
+                const uint64_t ins1 = ballot(ins && gpt_s == 0), ins2 = ballot(ins && gpt_s == 1);
                 const bool acc2 = pair && beat == 0;
-                const bool wr = low && (gpt == 0 || acc2);
+                const bool wr = low && (gpt_s == 0 || acc2);
                 if (wr) {
                     s_psi[q] = tf;
                     s_tag[q] = kBand | kInBand;
                 }
                 // KNOWN_NEW unless KNOWN_FIX; the points leave the band
-                if (lane == 48 || (lane == 49 && acc2))
+                if (ln_s == 48 || (ln_s == 49 && acc2))
                     s_tag[q] = ((tq & kStatus) == kKnownFix) ? kKnownFix : kKnownNew;
                 FMM_CYC(4);
                 FMM_CYC_COUNT(12, acc2 ? 2 : 1);
                 FMM_CYC_COUNT(16, 1);  // two-point steps taken, and how many accepted p2
                 FMM_CYC_COUNT(17, acc2 ? 1 : 0);
                 if (!acc2) {  // Remove_Min of p1: the last slot moves into its hole
-                    if (lane == 50 && m1.slot != n - 1) s_band[m1.slot] = (uint16_t)last1;
+                    if (ln_s == 50 && m1.slot != n - 1) s_band[m1.slot] = (uint16_t)last1;
                     n -= 1;
                 } else {
                     // Remove_Min of both: the holes below n - 2 take the entries of the last
@@ -388,8 +393,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     }
                     // the fillers in order: slot e2's entry if it is not a hole, then e1's
                     const bool e2_stays = e2 != s1 && e2 != s2;
-                    if (lane == 50 && h0 >= 0) s_band[h0] = e2_stays ? last2 : last1;
-                    if (lane == 51 && h1 >= 0) s_band[h1] = last1;  // both fillers: e2's, e1's
+                    if (ln_s == 50 && h0 >= 0) s_band[h0] = e2_stays ? last2 : last1;
+                    if (ln_s == 51 && h1 >= 0) s_band[h1] = last1;  // both fillers: e2's, e1's
                     n -= 2;
                     ++npops;
                 }
