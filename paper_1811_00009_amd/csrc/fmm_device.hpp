@@ -330,6 +330,35 @@ __device__ __forceinline__ void copy_band(D *dst, const S *src, int n, int tid)
     }
 }
 
+// Load the first m entries of a block's band array into the LDS band of SLOTS entries and
+// set the LDS slots [m, SLOTS) to 0: tile point 0 (a corner ghost, psi +inf, never in a
+// band), so that a scan of whole 8-slot groups needs no bounds test.  The march keeps
+// this while it runs: each slot that Remove_Min vacates is set to 0 again.
+template <int NT, int SLOTS>
+__device__ __forceinline__ void load_band_lds(FMM_LDS v4u *dst, const v4u *src, int m, int tid)
+{
+    static_assert(SLOTS % 8 == 0, "whole 16-byte groups");
+    constexpr int NV = SLOTS / 8;
+    const int nvec = (m + 7) >> 3;
+    for (int v0 = 0; v0 < NV; v0 += 4 * NT) {
+        v4u r[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + tid + j * NT;
+            r[j] = src[v < nvec ? v : 0];  // index 0 is always in bounds; masked below
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int v = v0 + tid + j * NT;
+            const int c = m - 8 * v;  // band entries in this group (<= 0: none)
+            uint32_t w[4] = {r[j].x, r[j].y, r[j].z, r[j].w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) w[i] = c >= 2 * i + 2 ? w[i] : (c == 2 * i + 1 ? (w[i] & 0xffffu) : 0u);
+            if (v < NV) dst[v] = v4u{w[0], w[1], w[2], w[3]};
+        }
+    }
+}
+
 // ---------------------------------------------------------------- cross-lane min
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x)
 {
@@ -570,7 +599,8 @@ __device__ __forceinline__ MinPick<R> band_argmin(const FMM_LDS uint16_t *s_band
 }
 
 // The two smallest (psi, key) entries of a band of at most 1024 slots, all in LDS, marched
-// by one wave (the two-point step of march_block).  Each lane takes the minimum of its
+// by one wave (the two-point step of march_block), whose LDS slots beyond n hold tile
+// point 0 (load_band_lds).  Each lane takes the minimum of its
 // slots and, with that slot left out, the next one (two shallow trees each, as in
 // band_chunk_min); the cross-lane step runs once on the lanes' minima and once more with
 // the winning lane offering its second.  Slots per lane as in band_argmin: 1, 2 or 4 for
@@ -674,12 +704,12 @@ __device__ __forceinline__ void lane_slots_top2(const FMM_LDS uint16_t *s_band, 
     } else {
         w[0] = s_band[base];
     }
+    // slots at n and beyond hold tile point 0 (psi +inf): no bounds test
     uint32_t ids[S], ks[S];
     R vs[S];
 #pragma unroll
     for (int j = 0; j < S; ++j) {
-        const uint32_t id = (w[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
-        ids[j] = (uint32_t)(base + j) < (uint32_t)n ? id : 0u;  // tile point 0: +inf
+        ids[j] = (w[j >> 1] >> ((j & 1) * 16)) & 0xffffu;
         ks[j] = (ids[j] << 16) | (uint32_t)(base + j);
     }
 #pragma unroll

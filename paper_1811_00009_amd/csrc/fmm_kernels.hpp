@@ -186,8 +186,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         copy_vec16<NT, TAGB / 16>(reinterpret_cast<FMM_LDS v4u *>(s_tag),
                                   reinterpret_cast<const v4u *>(g_tag), tid);
     }
-    copy_band<NT>(reinterpret_cast<FMM_LDS v4u *>(s_band), reinterpret_cast<const v4u *>(g_band),
-                  n < cap ? n : cap, tid);
+    load_band_lds<NT, Gm::BANDC>(reinterpret_cast<FMM_LDS v4u *>(s_band), reinterpret_cast<const v4u *>(g_band),
+                                 n < cap ? n : cap, tid);
     FMM_LDS R *s_rhs = reinterpret_cast<FMM_LDS R *>(lds + L::rhs_off);
     if constexpr (!TL) {
         // the tile is marched where it is; h^2/F^2 is read from memory as needed
@@ -378,6 +378,9 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 FMM_CYC_COUNT(12, acc2 ? 2 : 1);
                 FMM_CYC_COUNT(16, 1);  // two-point steps taken, and how many accepted p2
                 FMM_CYC_COUNT(17, acc2 ? 1 : 0);
+                // the slots that Remove_Min vacates (the last one or two) go back to tile
+                // point 0; an insert below may take them again (its store comes later)
+                if (ln_s == 52 || (ln_s == 53 && acc2)) s_band[n - 1 - (ln_s - 52)] = 0;
                 if (!acc2) {  // Remove_Min of p1: the last slot moves into its hole
                     if (ln_s == 50 && m1.slot != n - 1) s_band[m1.slot] = (uint16_t)last1;
                     n -= 1;
@@ -431,7 +434,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             exit_min = mp.v;
             break;
         }
-        n -= 1;  // Remove_Min: the last slot moves into the hole (lane 7 below)
+        n -= 1;  // Remove_Min: the last slot moves into the hole (lanes 25-26 below)
         // Update_Neighbors(p): quads 0-5 take the six face neighbours (interior only)
         if (wid == 0) {
             // h^2/F^2 of the lane's neighbour from device memory, issued before anything
@@ -474,12 +477,14 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                     thi[ax] = s_tag[qs + off];
                 }
             }
-            // Remove_Min: lane 25 moves the band's last slot into the hole.  The branch on
-            // the wave-uniform n < cap keeps the usual all-LDS case free of any wait on
+            // Remove_Min: lane 25 moves the band's last slot into the hole, and lane 26 sets
+            // the vacated LDS slot to tile point 0 (the band beyond n holds it).  The branch
+            // on the wave-uniform n < cap keeps the usual all-LDS case free of any wait on
             // device memory (the h^2/F^2 load above stays in flight until the solve).
             if (n < cap) {
                 const uint16_t last = (uint16_t)__builtin_amdgcn_readfirstlane(s_band[n]);
-                if (lane == 25) s_band[mp.slot] = last;  // mp.slot <= n < cap
+                if (lane == 25) s_band[mp.slot] = mp.slot == n ? (uint16_t)0 : last;  // mp.slot <= n < cap
+                if (lane == 26 && mp.slot != n) s_band[n] = 0;
             } else {
                 // every lane reads the same slot; taking it as a wave-uniform value also
                 // completes the load inside this branch
