@@ -657,6 +657,48 @@ __device__ __forceinline__ bool far_apart(int a, int b)
     }
 }
 
+// FP32: the same two smallest entries from 64-bit keys value bits << 32 | (index << 16 |
+// slot).  psi >= +0, so the bit patterns order like the values, and the low words are
+// unique: the unsigned order of the keys is the (psi, key) order.  A top-2 network: pairs
+// sorted, then sorted pairs merged (first = the smaller first; second = the smaller of the
+// other first and the winner's second), one compare and two 32-bit selects per choice.
+__device__ __forceinline__ void sort2_u64(uint64_t &a, uint64_t &b)
+{
+    const bool c = b < a;
+    const uint64_t lo = c ? b : a, hi = c ? a : b;
+    a = lo;
+    b = hi;
+}
+__device__ __forceinline__ void merge_top2_u64(uint64_t &a1, uint64_t &a2, uint64_t b1, uint64_t b2)
+{
+    const bool c = b1 < a1;
+    const uint64_t f = c ? b1 : a1, o = c ? a1 : b1, w2 = c ? b2 : a2;
+    a1 = f;
+    a2 = o < w2 ? o : w2;
+}
+template <int S>
+__device__ __forceinline__ void lane_top2_f32(const float (&vs)[S], const uint32_t (&ks)[S], uint64_t &x1,
+                                              uint64_t &x2)
+{
+    uint64_t x[S];
+#pragma unroll
+    for (int j = 0; j < S; ++j) x[j] = ((uint64_t)__float_as_uint(vs[j]) << 32) | ks[j];
+    if constexpr (S == 1) {
+        x1 = x[0];
+        x2 = ~0ull;
+    } else {
+#pragma unroll
+        for (int j = 0; j < S; j += 2) sort2_u64(x[j], x[j + 1]);
+#pragma unroll
+        for (int w = 2; w < S; w *= 2) {
+#pragma unroll
+            for (int j = 0; j < S; j += 2 * w) merge_top2_u64(x[j], x[j + 1], x[j + w], x[j + w + 1]);
+        }
+        x1 = x[0];
+        x2 = x[1];
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ bool key_less(R va, uint32_t ka, R vb, uint32_t kb)
 {
@@ -714,7 +756,16 @@ __device__ __forceinline__ void lane_slots_top2(const FMM_LDS uint16_t *s_band, 
     }
 #pragma unroll
     for (int j = 0; j < S; ++j) vs[j] = s_psi[ids[j]];
-    lane_top2<R, S>(vs, ks, v1, k1, v2, k2);
+    if constexpr (sizeof(R) == 4) {
+        uint64_t x1, x2;
+        lane_top2_f32<S>(vs, ks, x1, x2);
+        v1 = __uint_as_float((uint32_t)(x1 >> 32));
+        k1 = (uint32_t)x1;
+        v2 = __uint_as_float((uint32_t)(x2 >> 32));
+        k2 = (uint32_t)x2;
+    } else {
+        lane_top2<R, S>(vs, ks, v1, k1, v2, k2);
+    }
 }
 
 template <typename R, typename PsiP>
@@ -733,7 +784,17 @@ __device__ __forceinline__ void band_top2(const FMM_LDS uint16_t *s_band, PsiP s
             R u1, u2;
             uint32_t l1, l2;
             lane_slots_top2<R, 8, PsiP>(s_band, s_psi, n, 512 + 8 * lane, u1, l1, u2, l2);
-            top2_merge<R>(v1, k1, v2, k2, u1, l1, u2, l2);
+            if constexpr (sizeof(R) == 4) {
+                uint64_t a1 = ((uint64_t)__float_as_uint(v1) << 32) | k1, a2 = ((uint64_t)__float_as_uint(v2) << 32) | k2;
+                merge_top2_u64(a1, a2, ((uint64_t)__float_as_uint(u1) << 32) | l1,
+                               ((uint64_t)__float_as_uint(u2) << 32) | l2);
+                v1 = __uint_as_float((uint32_t)(a1 >> 32));
+                k1 = (uint32_t)a1;
+                v2 = __uint_as_float((uint32_t)(a2 >> 32));
+                k2 = (uint32_t)a2;
+            } else {
+                top2_merge<R>(v1, k1, v2, k2, u1, l1, u2, l2);
+            }
         }
     }
     FMM_CYC(1);
