@@ -506,6 +506,47 @@ __device__ __forceinline__ void band_small_min(const FMM_LDS uint16_t *s_band, P
     k_out = km;
 }
 
+// The two smallest values (with multiplicity) over the lanes' sorted pairs (a1 <= a2),
+// left in every lane.  Each stage merges the lane's pair with that of a lane holding a
+// disjoint set of lanes (quad swaps, half-row and row mirrors, then the row and half-wave
+// swaps), which a top-2 merge needs: first = min(a1, b1), second = min(max(a1, b1),
+// min(a2, b2)).  The swaps return the two lanes' values in an order that depends on the
+// lane, the same for both words of the pair.
+__device__ __forceinline__ void top2_merge_u32(uint32_t &a1, uint32_t &a2, uint32_t b1, uint32_t b2)
+{
+    const uint32_t f = min(a1, b1), s = min(max(a1, b1), min(a2, b2));
+    a1 = f;
+    a2 = s;
+}
+template <int CTRL>
+__device__ __forceinline__ void wave_top2_stage(uint32_t &a1, uint32_t &a2)
+{
+    const uint32_t b1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a1, CTRL, 0xF, 0xF, false);
+    const uint32_t b2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)a2, CTRL, 0xF, 0xF, false);
+    top2_merge_u32(a1, a2, b1, b2);
+}
+__device__ __forceinline__ void wave_top2_u32(uint32_t &a1, uint32_t &a2)
+{
+    wave_top2_stage<0xB1>(a1, a2);   // quad_perm [1,0,3,2]
+    wave_top2_stage<0x4E>(a1, a2);   // quad_perm [2,3,0,1]
+    wave_top2_stage<0x141>(a1, a2);  // row_half_mirror
+    wave_top2_stage<0x140>(a1, a2);  // row_mirror
+    {
+        auto x = __builtin_amdgcn_permlane16_swap(a1, a1, false, false);
+        auto y = __builtin_amdgcn_permlane16_swap(a2, a2, false, false);
+        a1 = x[0];
+        a2 = y[0];
+        top2_merge_u32(a1, a2, x[1], y[1]);
+    }
+    {
+        auto x = __builtin_amdgcn_permlane32_swap(a1, a1, false, false);
+        auto y = __builtin_amdgcn_permlane32_swap(a2, a2, false, false);
+        a1 = x[0];
+        a2 = y[0];
+        top2_merge_u32(a1, a2, x[1], y[1]);
+    }
+}
+
 // Cross-lane step of Locate_Min within one wave: the minimum value over the lanes (high
 // then low word for FP64), then the smallest key among the lanes holding it -- usually one
 // lane does, and its key is read directly; equal values in several lanes take the
@@ -798,6 +839,33 @@ __device__ __forceinline__ void band_top2(const FMM_LDS uint16_t *s_band, PsiP s
         }
     }
     FMM_CYC(1);
+    if constexpr (sizeof(R) == 4) {
+        // FP32: the two smallest values over the lanes at once.  When they differ, the first
+        // occurs once in the band (a second copy would be some lane's first or second), so
+        // one lane holds it as its first; the second is the smallest offer, the winning
+        // lane offering its second and every other lane its first, and ties among the
+        // offers take the smallest key.  Equal values take the general path below.
+        uint32_t f = __float_as_uint(v1), s2 = __float_as_uint(v2);
+        wave_top2_u32(f, s2);
+        f = __builtin_amdgcn_readfirstlane(f);
+        s2 = __builtin_amdgcn_readfirstlane(s2);
+        if (f != s2) {
+            const uint64_t m1 = ballot(__float_as_uint(v1) == f);
+            const int L = (int)__builtin_ctzll(m1);
+            const uint32_t mk = (uint32_t)__builtin_amdgcn_readlane((int)k1, L);
+            const bool own = lane == L;
+            const uint32_t ov = own ? __float_as_uint(v2) : __float_as_uint(v1), ok = own ? k2 : k1;
+            const uint64_t m2 = ballot(ov == s2);
+            uint32_t nk;
+            if (__builtin_popcountll(m2) == 1) nk = (uint32_t)__builtin_amdgcn_readlane((int)ok, (int)__builtin_ctzll(m2));
+            else nk = wave_min_u32(ov == s2 ? ok : ~0u);
+            nk = __builtin_amdgcn_readfirstlane(nk);
+            a = MinPick<R>{__uint_as_float(f), (int)(mk >> 16), (int)(mk & 0xffffu)};
+            b = MinPick<R>{__uint_as_float(s2), (int)(nk >> 16), (int)(nk & 0xffffu)};
+            FMM_CYC(2);
+            return;
+        }
+    }
     uint32_t mh, ml, mk;
     wave_pick<R>(v1, k1, mh, ml, mk);
     mh = __builtin_amdgcn_readfirstlane(mh);
