@@ -29,6 +29,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -40,14 +41,24 @@ HBM_PEAK_GBS = 8000.0
 ALGO_BYTES_PER_POINT = {"f32": 8, "f64": 16}  # read F once, write psi once
 
 
-def kernel_source_hash():
+def source_code_text(text):
+    """C++ source text without its comments and with its blank space collapsed: what a
+    change to the compiled kernels has to change."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(csrc=None):
+    """Hash of the kernel sources (comments and blank space left out, so that editing a
+    comment keeps the profiles measured on the same code valid)."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1811_00009_amd", "csrc")
+    csrc = csrc or os.path.join(ROOT, "paper_1811_00009_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
+            with open(os.path.join(csrc, name), encoding="utf-8") as f:
                 h.update(name.encode())
-                h.update(f.read())
+                h.update(source_code_text(f.read()).encode())
     return h.hexdigest()[:16]
 
 

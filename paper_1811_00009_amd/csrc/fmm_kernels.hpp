@@ -140,12 +140,12 @@ __device__ __forceinline__ ListSink launch_sink(const KParams<R> &kp, int c)
 // the tile back, record the new band minimum and raise the exchange flag of
 // every neighbour whose ghost layer meets the updated boundary points.
 //
-// One accepted point costs two LDS round trips for Locate_Min (a 16-byte read
-// of 8 band slots per lane, then the 8 psi values) and one or two for
-// Update_Neighbors (lanes 0-5 read the neighbour's tag and psi while lane 6
-// reads the accepted point's tag and lane 7 the band's last slot; the six
-// stencils in the same round trip when h^2/F^2 is in LDS, else in a second one
-// that covers the h^2/F^2 load from device memory, issued first).
+// One step costs two LDS round trips for Locate_Min (a 16-byte read of 8 band
+// slots per lane, then the 8 psi values) and one or two for Update_Neighbors
+// (the quads read their neighbour's tag and psi while single lanes read the
+// accepted points' tags and the band's last slots; the stencils in the same
+// round trip, except in the one-point step with h^2/F^2 in device memory, where
+// a second one covers that load, issued first).
 template <typename R, int B, int W>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
                             const ListSink &sink, char *smem, unsigned long long &pops_acc, bool &a_out,
