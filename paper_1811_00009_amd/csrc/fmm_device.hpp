@@ -275,8 +275,10 @@ struct Lds {
     static constexpr size_t bytes = scr_off + 16 * 8 + 64;
     // Waves per SIMD that the LDS footprint allows (160 KB per CU, 4 SIMDs).  The
     // register budget of the march kernels is capped to match, up to 4 waves (128
-    // registers) for one FP32 wave per block and 3 waves (168 registers) otherwise:
-    // below that the march would spill.
+    // registers) for one FP32 wave per block and 3 waves (168 registers) otherwise.
+    // At 128 registers the one-wave FP32 kernels of 4^3 and 8^3 blocks spill, almost
+    // all of it outside the loop of march steps; 168 registers at 8^3 blocks (12
+    // instead of 14 resident per CU) measured slower.
     static constexpr int wgs_per_cu = (int)(163840 / (bytes + 128));
     static constexpr int lds_waves_per_simd = (wgs_per_cu * W + 3) / 4;
     // a march in device memory (32^3 blocks) is not bound by LDS: three waves per SIMD
