@@ -674,8 +674,35 @@ __device__ __forceinline__ void lane_top2(const R (&vs)[S], const uint32_t (&ks)
     k2 = k2m;
 }
 
-// Whether tile points a and b (indices i + P j + P^2 k) lie at Manhattan distance >= 4, the
-// condition for taking two points in one march step.  For P >= 8 it is decided from the
+// The index offsets di + P dj + P^2 dk of the 62 displacements of Manhattan length 1 to 3,
+// one per lane (the last two lanes hold 0, which no pair of distinct points has).  Two
+// tile points at Manhattan distance below 4 differ by one of them, whatever P, so a pair
+// whose index difference matches no lane lies at distance >= 4, the condition for taking
+// two points in one march step.  A distant pair whose difference equals a short
+// displacement's offset is declined as well (at P = 18, 0.09 % of the distant pairs),
+// which costs one one-point step and no correctness.
+struct CloseOffsets {
+    int off[64];
+};
+template <int P>
+constexpr CloseOffsets make_close_offsets()
+{
+    CloseOffsets c{};
+    int n = 0;
+    for (int dk = -3; dk <= 3; ++dk)
+        for (int dj = -3; dj <= 3; ++dj)
+            for (int di = -3; di <= 3; ++di) {
+                const int m = (di < 0 ? -di : di) + (dj < 0 ? -dj : dj) + (dk < 0 ? -dk : dk);
+                if (m >= 1 && m <= 3) c.off[n++] = di + P * dj + P * P * dk;
+            }
+    for (; n < 64; ++n) c.off[n] = 0;
+    return c;
+}
+template <int P>
+__device__ const CloseOffsets kCloseOffsets = make_close_offsets<P>();
+
+// The same condition for tile points a and b (indices i + P j + P^2 k) without the table,
+// for march kernels whose register budget has no room for the lane's offset.  For P >= 8 it is decided from the
 // index difference d = b - a alone: a pair closer than 4 has d = di + P dj + P^2 dk with
 // |di| + |dj| + |dk| <= 3, and the decomposition below (offsets that keep every step
 // non-negative for such d) recovers exactly those (di, dj, dk), so every close pair is
@@ -699,6 +726,7 @@ __device__ __forceinline__ bool far_apart(int a, int b)
         return (di < 0 ? -di : di) + (dj < 0 ? -dj : dj) + (dk < 0 ? -dk : dk) >= 4;
     }
 }
+
 
 // FP32: the same two smallest entries from 64-bit keys value bits << 32 | (index << 16 |
 // slot).  psi >= +0, so the bit patterns order like the values, and the low words are

@@ -146,7 +146,10 @@ __device__ __forceinline__ ListSink launch_sink(const KParams<R> &kp, int c)
 // accepted points' tags and the band's last slots; the stencils in the same
 // round trip, except in the one-point step with h^2/F^2 in device memory, where
 // a second one covers that load, issued first).
-template <typename R, int B, int W>
+// LANE_PAIR: the two-point step's pair test by the lanes' table of short displacements (one
+// compare and a ballot), else by the index difference (scalar arithmetic); the batch kernel
+// takes the latter, since the table's register spills there at 8^3 blocks.
+template <typename R, int B, int W, bool LANE_PAIR = true>
 __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd, double bound,
                             const ListSink &sink, char *smem, unsigned long long &pops_acc, bool &a_out,
                             int &n_out, int &pops_out FMM_CYC_PARAM)
@@ -236,6 +239,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
         flo[ax] = (own && (gdir & 1)) ? kKnownFix : 0u;
         fhi[ax] = (own && !(gdir & 1)) ? kKnownFix : 0u;
     }
+    // the pair test of the two-point step: the lane's offset of a short displacement
+    const int close_off = LANE_PAIR ? kCloseOffsets<P>.off[lane] : 0;
     uint32_t mine = 0;  // faces of Upsilon, recorded as points are lowered (tile in memory)
     constexpr int kMid = (B / 2) * (1 + P + P * P);  // an interior point of the tile
     bool active = true;
@@ -254,7 +259,7 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
             if (n <= cap) {
                 // Two steps of Alg. 4 at once.  p1 is the band's minimum; p2, the next entry,
                 // is taken with it only when it lies at Manhattan distance >= 4 from p1
-                // (far_apart, which may decline a few such pairs as well): then p1's
+                // (kCloseOffsets or far_apart, which may decline a few such pairs as well): then p1's
                 // step (p1 and its face neighbours written, their neighbours read) and p2's
                 // touch disjoint points.  p2 is the point the sequential march accepts next
                 // unless p1's step lowers a point below it, which is checked once the roots
@@ -278,7 +283,8 @@ __device__ void march_block(const KParams<R> &kp, int64_t ib, const ProbDesc &pd
                 int p2 = p1;
                 bool pair = false;
                 if (n >= 2 && !(m2.v > rbound) && npops < pop_cap) {
-                    pair = far_apart<P>(p1, m2.idx);
+                    if constexpr (LANE_PAIR) pair = ballot(close_off == m2.idx - p1) == 0ull;
+                    else pair = far_apart<P>(p1, m2.idx);
                     if (pair) p2 = m2.idx;
                 }
                 // the lane's quad group, kk and lane id, re-read in each step: the lane
@@ -1388,7 +1394,7 @@ __global__ void __launch_bounds__(64 * W)
                     ++tot.tile_loads;
                     bool a;
                     int nbb, np;
-                    march_block<R, B, W>(kp, ib, pd, bound, sink, smem, tot.pops, a, nbb, np FMM_CYC_ARG);
+                    march_block<R, B, W, false>(kp, ib, pd, bound, sink, smem, tot.pops, a, nbb, np FMM_CYC_ARG);
                     if (tid == 0 && a) append_next<R>(kp, sink, r, ib, max(np, nbb), nbb, s_feat);
                 }
             }
